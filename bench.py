@@ -1,0 +1,186 @@
+#!/usr/bin/env python3
+"""Throughput of the MSC-preserving correction on one MI355X.
+
+A step is one full correction of one field (setup, gradient of f, separatrices of f, C/S loop
+to convergence, outputs) through the C ABI, with f and g_hat resident in HBM.  The default
+workload is the 2048x2048 field (256 Gaussians + 4-octave value noise, g_hat = f + U[-xi, xi],
+xi = 1e-4 * range, tier 4, q_max 6).
+
+Prints one JSON line: MB/s of fp32 input field (4*N bytes per step / step time), per-step
+latency percentiles, the roofline of the dominant kernel (measured with HIP events on the
+library's launch stream over the timed steps), and the plain CPU oracle timed on a bounded
+crop of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "MSC-correction MB/s of fp32 field to convergence; p50/p99 batch latency"
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic bytes per work unit of each kernel family ("Kernels and rooflines").
+# Planes per vertex: 6 (2D), 26 (3D).
+def bytes_per_unit(family: str, ndim: int) -> float:
+    nb = 6 if ndim == 2 else 26
+    return {
+        "gradient": 4.0 + nb,     # read the field once, write every cell's code byte
+        "classify": 2.0 * nb,     # read f and g code planes
+        "apply": 1.0,             # read the request byte (edited vertices add 14 B each)
+        "sstep": 10.0,            # branch cell id + branch id + f and g code bytes
+        "setup": 18.0,            # read f, g_hat; write floor, g, state, request
+    }.get(family, 0.0)
+
+
+def workload(name: str):
+    from paper_2409_17346_amd import synth
+    if name == "large2d":
+        return synth.config_large2d()
+    if name == "small2d":
+        return synth.config_small2d()
+    if name == "atoms3d":
+        return synth.config_atoms3d()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def traffic_from_profiles(kernel_file: str, family: str, ndim: int, units_per_launch: float):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it still matches
+    the kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", kernel_file)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    src = open(os.path.join(ROOT, "paper_2409_17346_amd", "csrc", "dmt_kernels.h"), "rb").read()
+    if kv.get("kernels_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(w, crop: int):
+    """The oracle (single thread, as written) on a crop x crop corner of the same workload."""
+    import numpy as np
+    import oracle
+    if w.f.ndim == 2:
+        f = np.ascontiguousarray(w.f[:crop, :crop])
+        g = np.ascontiguousarray(w.g_hat[:crop, :crop])
+        cx = oracle.Complex.grid(f.shape[1], f.shape[0], 1)
+    else:
+        f = np.ascontiguousarray(w.f[:crop, :crop, :crop])
+        g = np.ascontiguousarray(w.g_hat[:crop, :crop, :crop])
+        cx = oracle.Complex.grid(f.shape[2], f.shape[1], f.shape[0])
+    t0 = time.perf_counter()
+    r = oracle.correct(cx, f.reshape(-1), g.reshape(-1), w.xi, w.tier, w.q_max)
+    dt = time.perf_counter() - t0
+    return {"value": round(4.0 * f.size / dt / 1e6, 4), "unit": "MB/s", "cores": 1, "kind": "oracle",
+            "sample": f"{'x'.join(map(str, f.shape))} corner crop of the same field and g_hat, full correction "
+                      f"to convergence ({r['stats']['iterations']} iterations) in {dt:.1f} s on one host thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="large2d", choices=["large2d", "small2d", "atoms3d"])
+    ap.add_argument("--cpu-crop", type=int, default=256)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the correction of one field runs on one "
+              f"MI355X and this build has no multi-GPU path.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2409_17346_amd import dmt
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    w = workload(args.workload)
+    print(f"[bench] workload {w.name} shape {w.f.shape} xi {w.xi:.6g}", file=sys.stderr, flush=True)
+    ctx = dmt.Context(0)
+    f = torch.from_numpy(w.f).cuda()
+    gh = torch.from_numpy(w.g_hat).cuda()
+    g_out = torch.empty_like(f)
+    q_out = torch.empty(f.shape, dtype=torch.uint8, device="cuda")
+    n = f.numel()
+
+    for i in range(args.warmup):
+        r = dmt.dmt_correct(ctx, f, gh, w.xi, w.tier, w.q_max, want_edits=False, g_out=g_out, q_out=q_out)
+        print(f"[bench] warmup {i}: {r.status} {r.stats}", file=sys.stderr, flush=True)
+
+    dmt.dmt_profile_enable(ctx, True)
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ts = time.perf_counter()
+        r = dmt.dmt_correct(ctx, f, gh, w.xi, w.tier, w.q_max, want_edits=False, g_out=g_out, q_out=q_out)
+        lat.append(time.perf_counter() - ts)
+        print(f"[bench] step {i}: {lat[-1] * 1e3:.1f} ms {r.status} iterations={r.stats['iterations']}",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = dmt.dmt_profile_read(ctx)
+    dmt.dmt_profile_enable(ctx, False)
+
+    value = 4.0 * n * args.steps / elapsed / 1e6
+    lat_sorted = sorted(lat)
+
+    def pct(p):
+        k = min(len(lat_sorted) - 1, max(0, int(round(p / 100.0 * (len(lat_sorted) - 1)))))
+        return round(lat_sorted[k] * 1e3, 3)
+
+    ndim = w.ndim
+    fam = max((k for k in prof if bytes_per_unit(k, ndim) > 0 and prof[k]["launches"]), key=lambda k: prof[k]["ms"])
+    p = prof[fam]
+    avg_ms = p["ms"] / p["launches"]
+    units_per_launch = p["units"] / p["launches"]
+    alg_bytes = bytes_per_unit(fam, ndim) * units_per_launch
+    achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
+    traffic = traffic_from_profiles(f"{fam}_{w.name}.txt", fam, ndim, units_per_launch)
+    line = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "MB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "dims": list(w.dims), "tier": w.tier, "q_max": w.q_max,
+                   "rel_error_bound": w.meta.get("rel"), "iterations": r.stats["iterations"],
+                   "c_iterations": r.stats["c_iterations"], "s_iterations": r.stats["s_iterations"]},
+        "latency_ms": {"p50": pct(50), "p99": pct(99)},
+        "roofline": {"bound": "hbm", "kernel": fam, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "launches": p["launches"], "avg_launch_us": round(avg_ms * 1e3, 3),
+                     "alg_bytes_per_launch": int(alg_bytes)},
+        "kernel_ms": {k: round(v["ms"], 3) for k, v in prof.items()},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(w, args.cpu_crop)
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

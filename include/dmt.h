@@ -1,0 +1,206 @@
+/* dmt.h - C ABI of the MI355X (gfx950) library for the Morse-Smale-complex-preserving
+ * correction stage of error-bounded lossy compression (DMTz, arXiv 2409.17346).
+ *
+ * Problem (Section 4.1, "Problem Statement"): given an original scalar field f and a
+ * decompressed field g_hat on the same grid with |g_hat_i - f_i| <= xi, produce edits
+ * delta_i and the corrected field g = g_hat + delta with |f_i - g_i| <= xi for every vertex
+ * and a discrete Morse-Smale complex identical to that of f.
+ *
+ * Grid and complex.  Scalars live on the vertices of an nx*ny*nz regular grid (nz == 1 for
+ * 2D), x fastest: vertex id v = x + nx*(y + ny*z).  The grid is triangulated by the
+ * Freudenthal/Kuhn rule (two triangles per square along the (1,1) diagonal, six tetrahedra
+ * per cube along the (1,1,1) diagonal; the paper's "regular grid-based triangulation" with
+ * "six tetrahedra per cube", Section 4.8.1).
+ *
+ * Cell ids.  A cell is {a, a+c1, ..., a+cd} with a its componentwise-minimum vertex (the
+ * anchor) and 0 < c1 < ... < cd a chain of direction bit sets (bit 0 = +x, bit 1 = +y,
+ * bit 2 = +z, strict bitwise inclusion).  The chains of each dimension are sorted
+ * lexicographically by their bit values and numbered 0..T_d-1:
+ *   2D: T = {1, 3, 2}       (vertices, edges, triangles)
+ *   3D: T = {1, 7, 12, 6}   (vertices, edges, triangles, tetrahedra)
+ * Cell id = a * T_d + type, one id space per dimension; ids whose cell leaves the grid are
+ * holes ("does not exist").  Ids are int64.
+ *
+ * Vertex order (Section 4.1, "Degeneracy handling"): a precedes b iff h_a < h_b, or
+ * h_a == h_b and a < b (simulation of simplicity; -0 == +0).  Non-finite values are rejected.
+ *
+ * Memory.  Every array argument is a DEVICE pointer owned by the caller unless its name ends
+ * in _host.  Nothing is freed by the library except its own context.  Calls are ordered on
+ * the given stream; a call returns after the results it reports on the host are known
+ * (it synchronises that stream when it returns host values).
+ *
+ * Errors.  Functions return dmt_status; no exception crosses the ABI.  dmt_last_error gives
+ * a message for the last failing call on a context.  Validation errors leave outputs
+ * untouched.  Contexts are not thread safe: use one per host thread.
+ */
+#ifndef DMT_H
+#define DMT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DMT_OK = 0,
+    DMT_W_NOT_CONVERGED = 1,   /* stalled or iteration cap hit; outputs valid and within bound */
+    DMT_E_INVALID = -1,        /* bad grid, options, xi or sizes */
+    DMT_E_BOUND = -2,          /* some |g_hat_i - f_i| > xi */
+    DMT_E_NONFINITE = -3,      /* NaN or Inf in an input field */
+    DMT_E_NOMEM = -4,          /* device allocation failed */
+    DMT_E_HIP = -5             /* other HIP runtime error */
+} dmt_status;
+
+/* Preservation tiers (Section 4.1, "Multitier preservation targets"). */
+typedef enum {
+    DMT_T1_EXTREMA = 1,        /* minima and maxima */
+    DMT_T2_CRITICAL = 2,       /* all critical cells */
+    DMT_T3_CONNECTIVITY = 3,   /* + each separatrix reaches the same extremum */
+    DMT_T4_GEOMETRY = 4        /* + each separatrix follows the same cells */
+} dmt_tier;
+
+typedef struct dmt_context dmt_context;
+
+typedef struct {
+    int32_t ndim;              /* 2 or 3; ndim == 2 requires nz == 1 */
+    int64_t nx, ny, nz;        /* every used extent >= 2; nx*ny*nz < 2^31 */
+} dmt_grid;
+
+typedef struct {
+    int32_t tier;              /* dmt_tier */
+    int32_t q_max;             /* 0..7: edit step xi / 2^q_max (Equation 2); the paper uses 6 */
+    int64_t max_iters;         /* cap on edit iterations (C + S); < 0 means no cap */
+    uint32_t flags;            /* reserved, must be 0 */
+} dmt_options;
+
+typedef struct {
+    int64_t iterations;        /* edit iterations applied (C + S) */
+    int64_t c_iterations;      /* iterations fixing false critical cells (Section 4.3) */
+    int64_t s_iterations;      /* iterations fixing separatrix troublemakers (Section 4.4) */
+    int64_t n_edited;          /* vertices with q_out != 0 */
+    int64_t n_quantized;       /* vertices with 1 <= q_out <= q_max */
+    int64_t n_lossless;        /* vertices with q_out == 0xFF */
+    int64_t residual_violations; /* violations left when not converged, else 0 */
+    int32_t converged;
+    int32_t stalled;           /* requests existed but every requested vertex was final */
+} dmt_stats;
+
+/* Per-iteration log record (int64 each): kind (1 = C, 2 = S), FP0, FN0, FP1, FN1, FP2, FN2,
+ * FP3, FN3 (false positive / negative critical cells by dimension), TM_desc, TM_asc
+ * (troublemaker branches fixed), n_req (vertices requested), changed, 0, 0, 0. */
+#define DMT_LOG_WORDS 16
+
+/* ---- context ----------------------------------------------------------------------------- */
+
+/* Creates a context bound to HIP device hip_device.  The context owns device scratch (grown on
+ * demand, freed by dmt_context_destroy) and the results of the last MSC extraction /
+ * correction. */
+dmt_status dmt_context_create(dmt_context **ctx, int hip_device);
+dmt_status dmt_context_destroy(dmt_context *ctx);
+const char *dmt_last_error(const dmt_context *ctx);
+
+/* Sizes of the per-dimension cell id spaces (N * T_d; 0 above ndim).  Host only. */
+dmt_status dmt_cell_id_space(const dmt_grid *grid, int64_t counts_host[4]);
+
+/* ---- setup (Section 4.2, Equation 2; Section 5 "relative error bound") ------------------ */
+
+/* xi = fl32(rel * (max f - min f)), the range taken in double precision. */
+dmt_status dmt_xi_from_relative(dmt_context *ctx, const dmt_grid *grid, const float *f, double rel,
+                                float *xi_host, hipStream_t stream);
+
+/* lo[i] = smallest fp32 >= f[i] - xi, hi[i] = largest fp32 <= f[i] + xi (exact arithmetic).
+ * lo is the floor Equation 2 drops a vertex to ("f_i - xi").  n elements. */
+dmt_status dmt_bounds(dmt_context *ctx, const float *f, int64_t n, float xi, float *lo, float *hi,
+                      hipStream_t stream);
+
+/* ---- discrete gradient and Morse-Smale complex (Section 3.1) ------------------------------ */
+
+/* Discrete gradient of field (Section 3.1 pairing of Shivashankar-Natarajan as spelled out in
+ * Section 4.2): for every cell id of every dimension d, up[off_d + id] = paired cofacet id (dim
+ * d+1) or -1, down[off_d + id] = paired facet id (dim d-1) or -1, where off_d is the sum of the
+ * id-space sizes of lower dimensions.  up and down hold sum_d counts[d] int64 each. */
+dmt_status dmt_gradient_pairs(dmt_context *ctx, const dmt_grid *grid, const float *field,
+                              int64_t *up, int64_t *down, hipStream_t stream);
+
+/* Items of an extracted MSC (all int64):
+ *  CRITd          ids of critical d-cells, ascending.
+ *  DESC_*         descending separatrices: for each critical edge (1-saddle) in id order, one
+ *                 branch per endpoint (endpoint id order): SADDLE[b], the vertex sequence
+ *                 CELLS[OFFSETS[b] .. OFFSETS[b+1]) from the endpoint to the minimum, and
+ *                 TERMINAL[b] (the minimum's vertex id).  OFFSETS has n_desc + 1 entries.
+ *  ASC_*          ascending separatrices: for each critical (n-1)-cell in id order, one branch
+ *                 per top-dimensional cofacet (id order): the top-cell sequence and TERMINAL =
+ *                 the maximum's id, or -1 if the path leaves through the domain boundary.
+ *  MIN_LABEL[v]   terminal of v's descending path (N entries).
+ *  MAX_LABEL[T]   terminal of top cell T's ascending path, -1 boundary, -2 for ids that do not
+ *                 exist (counts[ndim] entries). */
+enum {
+    DMT_MSC_CRIT0 = 0, DMT_MSC_CRIT1 = 1, DMT_MSC_CRIT2 = 2, DMT_MSC_CRIT3 = 3,
+    DMT_MSC_DESC_SADDLE = 10, DMT_MSC_DESC_OFFSETS = 11, DMT_MSC_DESC_CELLS = 12, DMT_MSC_DESC_TERMINAL = 13,
+    DMT_MSC_ASC_SADDLE = 20, DMT_MSC_ASC_OFFSETS = 21, DMT_MSC_ASC_CELLS = 22, DMT_MSC_ASC_TERMINAL = 23,
+    DMT_MSC_MIN_LABEL = 30, DMT_MSC_MAX_LABEL = 31
+};
+
+/* Extracts the MSC of field into the context (kept until the next extraction) and writes the
+ * length of every item to counts_host[item] (an array of 32 int64). */
+dmt_status dmt_extract_msc(dmt_context *ctx, const dmt_grid *grid, const float *field,
+                           int64_t counts_host[32], hipStream_t stream);
+/* Copies item of the last extraction into dst (device, cap int64 entries). */
+dmt_status dmt_msc_copy(dmt_context *ctx, int item, int64_t *dst, int64_t cap, hipStream_t stream);
+
+/* ---- correction (Sections 4.2-4.7) ------------------------------------------------------- */
+
+/* Runs the C-loop / S-loop correction until f's MSC (at the requested tier) is restored.
+ * f, g_hat: N floats.  Outputs: g_out (N floats, the corrected field) and q_out (N bytes:
+ * the quantized edit count 0..q_max, or 0xFF where the vertex was set to its floor and is
+ * stored losslessly).  Returns DMT_OK when converged, DMT_W_NOT_CONVERGED otherwise (outputs
+ * still valid and within bound).  The lossless edits and the per-iteration log of this call
+ * stay in the context for dmt_lossless_edits / dmt_iteration_log. */
+dmt_status dmt_correct(dmt_context *ctx, const dmt_grid *grid, const float *f, const float *g_hat,
+                       float xi, const dmt_options *opts, float *g_out, uint8_t *q_out,
+                       dmt_stats *stats_host, hipStream_t stream);
+
+/* Lossless edits of the last dmt_correct: vertex ids ascending and their final values.
+ * Writes min(count, cap) entries, returns the full count in count_host. */
+dmt_status dmt_lossless_edits(dmt_context *ctx, int64_t *idx_out, float *val_out, int64_t cap,
+                              int64_t *count_host, hipStream_t stream);
+
+/* Per-iteration log of the last dmt_correct (host memory, DMT_LOG_WORDS int64 per record). */
+dmt_status dmt_iteration_log(dmt_context *ctx, int64_t *log_host, int64_t cap, int64_t *count_host);
+
+/* Decoder (Section 4.7, Figure 5 decompression side): g = g_hat - q * xi/2^q_max rounded once,
+ * then the n_lossless (idx, val) pairs overwrite their vertices.  q == 0xFF entries must be
+ * listed in idx.  All arrays on the device. */
+dmt_status dmt_apply_edits(dmt_context *ctx, const float *g_hat, const uint8_t *q, int64_t n,
+                           const int64_t *idx, const float *val, int64_t n_lossless, float xi,
+                           int32_t q_max, float *g_out, hipStream_t stream);
+
+/* ---- kernel timing (roofline measurement) ------------------------------------------------ */
+
+/* Kernel families timed by dmt_profile_*: */
+enum {
+    DMT_PROF_GRADIENT = 0,  /* lower-star gradient pass, units = vertices */
+    DMT_PROF_CLASSIFY = 1,  /* critical-cell violation pass, units = anchors */
+    DMT_PROF_APPLY = 2,     /* Equation 2 edit pass, units = vertices */
+    DMT_PROF_SSTEP = 3,     /* separatrix troublemaker pass, units = branch cells */
+    DMT_PROF_SETUP = 4,     /* floors and validation, units = vertices */
+    DMT_PROF_MSC = 5,       /* critical cells + separatrix branches of f, units = vertices */
+    DMT_PROF_KERNELS = 6
+};
+
+/* Turns event timing of the kernel families on (1) or off (0) for later calls on ctx and
+ * clears what was recorded.  Events are recorded on the stream each kernel is launched on. */
+dmt_status dmt_profile_enable(dmt_context *ctx, int enable);
+/* Launch count, summed duration (ms) and summed work units of family kernel since the last
+ * dmt_profile_enable.  Waits for the recorded events. */
+dmt_status dmt_profile_read(dmt_context *ctx, int kernel, int64_t *launches_host, double *ms_total_host,
+                            int64_t *units_host);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DMT_H */

@@ -1,0 +1,295 @@
+"""Thin Python binding of the C ABI in include/dmt.h (argument marshalling only).
+
+Every function has the name of the C entry point it calls.  Fields are torch tensors on the
+GPU, shaped (ny, nx) for 2D or (nz, ny, nx) for 3D (x fastest, fp32, contiguous); the current
+torch stream of the tensor's device is passed as the HIP stream.  PyTorch provides device
+memory and streams only: all computation happens in the HIP library ``libdmt.so``.  There is
+no CPU fallback: if the library or a GPU is missing, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Dict, Tuple
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SO = os.path.join(HERE, "libdmt.so")
+
+DMT_OK = 0
+DMT_W_NOT_CONVERGED = 1
+STATUS_NAMES = {0: "ok", 1: "not_converged", -1: "invalid", -2: "bound", -3: "nonfinite", -4: "nomem",
+                -5: "hip"}
+LOG_WORDS = 16
+LOG_KEYS = ["kind", "FP0", "FN0", "FP1", "FN1", "FP2", "FN2", "FP3", "FN3", "TM_desc", "TM_asc", "n_req",
+            "changed"]
+
+MSC_ITEMS = {
+    "crit0": 0, "crit1": 1, "crit2": 2, "crit3": 3,
+    "desc_saddle": 10, "desc_offsets": 11, "desc_cells": 12, "desc_terminal": 13,
+    "asc_saddle": 20, "asc_offsets": 21, "asc_cells": 22, "asc_terminal": 23,
+    "min_label": 30, "max_label": 31,
+}
+
+# Names of every entry point declared in include/dmt.h.
+ABI_SYMBOLS = [
+    "dmt_context_create", "dmt_context_destroy", "dmt_last_error", "dmt_cell_id_space",
+    "dmt_xi_from_relative", "dmt_bounds", "dmt_gradient_pairs", "dmt_extract_msc", "dmt_msc_copy",
+    "dmt_correct", "dmt_lossless_edits", "dmt_iteration_log", "dmt_apply_edits", "dmt_profile_enable",
+    "dmt_profile_read",
+]
+
+PROF_KERNELS = {"gradient": 0, "classify": 1, "apply": 2, "sstep": 3, "setup": 4, "msc": 5}
+
+
+class DmtError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class dmt_grid(C.Structure):
+    _fields_ = [("ndim", C.c_int32), ("nx", C.c_int64), ("ny", C.c_int64), ("nz", C.c_int64)]
+
+
+class dmt_options(C.Structure):
+    _fields_ = [("tier", C.c_int32), ("q_max", C.c_int32), ("max_iters", C.c_int64), ("flags", C.c_uint32)]
+
+
+class dmt_stats(C.Structure):
+    _fields_ = [("iterations", C.c_int64), ("c_iterations", C.c_int64), ("s_iterations", C.c_int64),
+                ("n_edited", C.c_int64), ("n_quantized", C.c_int64), ("n_lossless", C.c_int64),
+                ("residual_violations", C.c_int64), ("converged", C.c_int32), ("stalled", C.c_int32)]
+
+    def as_dict(self) -> Dict[str, int]:
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+_lib = None
+VP = C.c_void_p
+P64 = C.POINTER(C.c_int64)
+
+
+def load_library(path: str = SO):
+    """Loads libdmt.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library {path} is missing: build it with `python -m paper_2409_17346_amd.build`")
+    L = C.CDLL(path)
+    L.dmt_context_create.argtypes = [C.POINTER(VP), C.c_int]
+    L.dmt_context_destroy.argtypes = [VP]
+    L.dmt_last_error.restype = C.c_char_p
+    L.dmt_last_error.argtypes = [VP]
+    L.dmt_cell_id_space.argtypes = [C.POINTER(dmt_grid), P64]
+    L.dmt_xi_from_relative.argtypes = [VP, C.POINTER(dmt_grid), VP, C.c_double, C.POINTER(C.c_float), VP]
+    L.dmt_bounds.argtypes = [VP, VP, C.c_int64, C.c_float, VP, VP, VP]
+    L.dmt_gradient_pairs.argtypes = [VP, C.POINTER(dmt_grid), VP, VP, VP, VP]
+    L.dmt_extract_msc.argtypes = [VP, C.POINTER(dmt_grid), VP, P64, VP]
+    L.dmt_msc_copy.argtypes = [VP, C.c_int, VP, C.c_int64, VP]
+    L.dmt_correct.argtypes = [VP, C.POINTER(dmt_grid), VP, VP, C.c_float, C.POINTER(dmt_options), VP, VP,
+                              C.POINTER(dmt_stats), VP]
+    L.dmt_lossless_edits.argtypes = [VP, VP, VP, C.c_int64, P64, VP]
+    L.dmt_iteration_log.argtypes = [VP, P64, C.c_int64, P64]
+    L.dmt_apply_edits.argtypes = [VP, VP, VP, C.c_int64, VP, VP, C.c_int64, C.c_float, C.c_int32, VP, VP]
+    L.dmt_profile_enable.argtypes = [VP, C.c_int]
+    L.dmt_profile_read.argtypes = [VP, C.c_int, P64, C.POINTER(C.c_double), P64]
+    for name in ABI_SYMBOLS:
+        if name != "dmt_last_error":
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def grid_of(t: torch.Tensor) -> dmt_grid:
+    if t.dim() == 2:
+        return dmt_grid(2, t.shape[1], t.shape[0], 1)
+    if t.dim() == 3:
+        return dmt_grid(3, t.shape[2], t.shape[1], t.shape[0])
+    raise ValueError("fields must be 2D (ny, nx) or 3D (nz, ny, nx)")
+
+
+def _dev(t: torch.Tensor, dtype=torch.float32) -> torch.Tensor:
+    if not t.is_cuda:
+        raise ValueError("expected a GPU tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"expected a contiguous {dtype} tensor")
+    return t
+
+
+def _stream(t: torch.Tensor):
+    return VP(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+class Context:
+    """Owns a dmt_context (device scratch + results of the last extraction / correction)."""
+
+    def __init__(self, device: int = 0):
+        self.L = load_library()
+        self.device = device
+        h = VP()
+        st = self.L.dmt_context_create(C.byref(h), device)
+        if st != DMT_OK:
+            raise DmtError(st, "dmt_context_create failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.dmt_context_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def check(self, st: int, allow=(DMT_OK,)):
+        if st not in allow:
+            raise DmtError(st, self.L.dmt_last_error(self.h).decode())
+        return st
+
+
+def dmt_context_create(device: int = 0) -> Context:
+    return Context(device)
+
+
+def dmt_cell_id_space(shape) -> Tuple[int, int, int, int]:
+    L = load_library()
+    g = dmt_grid(2, shape[1], shape[0], 1) if len(shape) == 2 else dmt_grid(3, shape[2], shape[1], shape[0])
+    out = (C.c_int64 * 4)()
+    st = L.dmt_cell_id_space(C.byref(g), out)
+    if st != DMT_OK:
+        raise DmtError(st, "invalid grid")
+    return tuple(int(x) for x in out)
+
+
+def dmt_xi_from_relative(ctx: Context, f: torch.Tensor, rel: float) -> float:
+    _dev(f)
+    xi = C.c_float()
+    g = grid_of(f)
+    ctx.check(ctx.L.dmt_xi_from_relative(ctx.h, C.byref(g), VP(f.data_ptr()), rel, C.byref(xi), _stream(f)))
+    return float(xi.value)
+
+
+def dmt_bounds(ctx: Context, f: torch.Tensor, xi: float):
+    _dev(f)
+    lo = torch.empty_like(f)
+    hi = torch.empty_like(f)
+    ctx.check(ctx.L.dmt_bounds(ctx.h, VP(f.data_ptr()), f.numel(), xi, VP(lo.data_ptr()), VP(hi.data_ptr()),
+                               _stream(f)))
+    return lo, hi
+
+
+def dmt_gradient_pairs(ctx: Context, field: torch.Tensor):
+    """Returns (up, down) int64 tensors over the concatenated per-dimension cell id spaces."""
+    _dev(field)
+    counts = dmt_cell_id_space(tuple(field.shape))
+    total = sum(counts)
+    up = torch.empty(total, dtype=torch.int64, device=field.device)
+    down = torch.empty(total, dtype=torch.int64, device=field.device)
+    g = grid_of(field)
+    ctx.check(ctx.L.dmt_gradient_pairs(ctx.h, C.byref(g), VP(field.data_ptr()), VP(up.data_ptr()),
+                                       VP(down.data_ptr()), _stream(field)))
+    return up, down, counts
+
+
+def dmt_extract_msc(ctx: Context, field: torch.Tensor) -> Dict[str, torch.Tensor]:
+    """Critical cells, separatrix branches and manifold labels of field, as int64 GPU tensors."""
+    _dev(field)
+    counts = (C.c_int64 * 32)()
+    g = grid_of(field)
+    ctx.check(ctx.L.dmt_extract_msc(ctx.h, C.byref(g), VP(field.data_ptr()), counts, _stream(field)))
+    out = {}
+    for name, item in MSC_ITEMS.items():
+        n = int(counts[item])
+        t = torch.empty(max(n, 0), dtype=torch.int64, device=field.device)
+        if n > 0:
+            ctx.check(ctx.L.dmt_msc_copy(ctx.h, item, VP(t.data_ptr()), n, _stream(field)))
+        out[name] = t
+    return out
+
+
+@dataclass
+class Result:
+    status: str
+    g: torch.Tensor
+    q: torch.Tensor
+    stats: Dict[str, int]
+    lossless_idx: torch.Tensor
+    lossless_val: torch.Tensor
+    log: torch.Tensor
+
+
+def dmt_correct(ctx: Context, f: torch.Tensor, g_hat: torch.Tensor, xi: float, tier: int = 4, q_max: int = 6,
+                max_iters: int = -1, want_edits: bool = True, g_out: torch.Tensor | None = None,
+                q_out: torch.Tensor | None = None) -> Result:
+    _dev(f)
+    _dev(g_hat)
+    if f.shape != g_hat.shape:
+        raise ValueError("f and g_hat differ in shape")
+    g_out = torch.empty_like(f) if g_out is None else g_out
+    q_out = torch.empty(f.shape, dtype=torch.uint8, device=f.device) if q_out is None else q_out
+    st = dmt_stats()
+    opts = dmt_options(tier, q_max, max_iters, 0)
+    g = grid_of(f)
+    rc = ctx.check(ctx.L.dmt_correct(ctx.h, C.byref(g), VP(f.data_ptr()), VP(g_hat.data_ptr()), xi, C.byref(opts),
+                                     VP(g_out.data_ptr()), VP(q_out.data_ptr()), C.byref(st), _stream(f)),
+                   allow=(DMT_OK, DMT_W_NOT_CONVERGED))
+    stats = st.as_dict()
+    idx = val = log = None
+    if want_edits:
+        idx, val = dmt_lossless_edits(ctx, f.device)
+        log = dmt_iteration_log(ctx)
+    return Result(STATUS_NAMES[rc], g_out, q_out, stats, idx, val, log)
+
+
+def dmt_lossless_edits(ctx: Context, device) -> Tuple[torch.Tensor, torch.Tensor]:
+    n = C.c_int64()
+    s = VP(torch.cuda.current_stream(device).cuda_stream)
+    ctx.check(ctx.L.dmt_lossless_edits(ctx.h, None, None, 0, C.byref(n), s))
+    idx = torch.empty(n.value, dtype=torch.int64, device=device)
+    val = torch.empty(n.value, dtype=torch.float32, device=device)
+    if n.value:
+        ctx.check(ctx.L.dmt_lossless_edits(ctx.h, VP(idx.data_ptr()), VP(val.data_ptr()), n.value, C.byref(n), s))
+    return idx, val
+
+
+def dmt_iteration_log(ctx: Context) -> torch.Tensor:
+    n = C.c_int64()
+    ctx.check(ctx.L.dmt_iteration_log(ctx.h, None, 0, C.byref(n)))
+    out = torch.zeros((n.value, LOG_WORDS), dtype=torch.int64)
+    if n.value:
+        ctx.check(ctx.L.dmt_iteration_log(ctx.h, C.cast(out.data_ptr(), P64), n.value, C.byref(n)))
+    return out
+
+
+def dmt_apply_edits(ctx: Context, g_hat: torch.Tensor, q: torch.Tensor, idx: torch.Tensor, val: torch.Tensor,
+                    xi: float, q_max: int) -> torch.Tensor:
+    _dev(g_hat)
+    _dev(q, torch.uint8)
+    out = torch.empty_like(g_hat)
+    m = idx.numel()
+    ctx.check(ctx.L.dmt_apply_edits(ctx.h, VP(g_hat.data_ptr()), VP(q.data_ptr()), g_hat.numel(),
+                                    VP(idx.data_ptr()) if m else None, VP(val.data_ptr()) if m else None, m, xi,
+                                    q_max, VP(out.data_ptr()), _stream(g_hat)))
+    return out
+
+
+def dmt_profile_enable(ctx: Context, enable: bool = True) -> None:
+    ctx.check(ctx.L.dmt_profile_enable(ctx.h, 1 if enable else 0))
+
+
+def dmt_profile_read(ctx: Context) -> Dict[str, Dict[str, float]]:
+    """Per kernel family: launches, total ms (HIP events on the launch stream), work units."""
+    out = {}
+    for name, k in PROF_KERNELS.items():
+        n = C.c_int64()
+        ms = C.c_double()
+        u = C.c_int64()
+        ctx.check(ctx.L.dmt_profile_read(ctx.h, k, C.byref(n), C.byref(ms), C.byref(u)))
+        out[name] = {"launches": int(n.value), "ms": float(ms.value), "units": int(u.value)}
+    return out

@@ -1,0 +1,198 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle, element by element.
+
+Everything on the correction path is comparisons plus one fused multiply-add per edit, so the
+required agreement is bit-exact: gradient pairs, critical cell ids, separatrix sequences and
+terminals, manifold labels, corrected field bits, quantized edit counts, lossless edits,
+statistics and the per-iteration log.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2409_17346_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dmt():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2409_17346_amd import dmt as D
+    D.load_library()
+    return D
+
+
+@pytest.fixture(scope="module")
+def ctx(dmt):
+    c = dmt.Context(0)
+    yield c
+    c.close()
+
+
+def _t(a, dtype=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def _shape3(shape):
+    return (shape[1], shape[0], 1) if len(shape) == 2 else (shape[2], shape[1], shape[0])
+
+
+GRAD_SHAPES = [(2, 2), (3, 3), (7, 5), (33, 65), (130, 67), (2, 2, 2), (5, 4, 3), (9, 17, 6), (31, 12, 20)]
+
+
+@pytest.mark.parametrize("shape", GRAD_SHAPES)
+@pytest.mark.parametrize("kind", ["uniform", "plateau", "const", "perm", "smooth"])
+def test_gradient_pairs(ctx, dmt, shape, kind):
+    f = synth.random_field(shape, kind, 3)
+    up, down, counts = dmt.dmt_gradient_pairs(ctx, _t(f))
+    cx = oracle.Complex.grid(*_shape3(shape))
+    oup, odn = oracle.gradient(cx, f.reshape(-1))
+    assert np.array_equal(up.cpu().numpy(), np.concatenate(oup))
+    assert np.array_equal(down.cpu().numpy(), np.concatenate(odn))
+
+
+MSC_SHAPES = [(3, 3), (16, 9), (64, 64), (129, 70), (3, 3, 3), (8, 7, 6), (17, 20, 13)]
+
+
+@pytest.mark.parametrize("shape", MSC_SHAPES)
+@pytest.mark.parametrize("kind", ["uniform", "plateau", "smooth"])
+def test_msc(ctx, dmt, shape, kind):
+    f = synth.random_field(shape, kind, 5)
+    m = dmt.dmt_extract_msc(ctx, _t(f))
+    cx = oracle.Complex.grid(*_shape3(shape))
+    o = oracle.msc(cx, f.reshape(-1))
+    for d in range(cx.top + 1):
+        assert np.array_equal(m[f"crit{d}"].cpu().numpy(), o.crit[d]), d
+    pairs = {"desc_saddle": o.desc_saddle, "desc_offsets": o.desc_offsets, "desc_cells": o.desc_cells,
+             "desc_terminal": o.desc_terminal, "asc_saddle": o.asc_saddle, "asc_offsets": o.asc_offsets,
+             "asc_cells": o.asc_cells, "asc_terminal": o.asc_terminal, "min_label": o.min_label,
+             "max_label": o.max_label}
+    for k, v in pairs.items():
+        assert np.array_equal(m[k].cpu().numpy(), v), k
+
+
+def test_bounds_and_xi(ctx, dmt):
+    rng = np.random.default_rng(2)
+    f = np.concatenate([rng.uniform(-3, 3, 5000), rng.uniform(-1e-5, 1e-5, 1000), [0.0, -0.0, 1e-4]]).astype(np.float32)
+    for xi in (1e-4, 0.37, 3e-39, 1.0):
+        lo, hi = dmt.dmt_bounds(ctx, _t(f), xi)
+        olo, ohi = oracle.bounds(f, xi)
+        assert np.array_equal(lo.cpu().numpy().view(np.uint32), olo.view(np.uint32))
+        assert np.array_equal(hi.cpu().numpy().view(np.uint32), ohi.view(np.uint32))
+    g = synth.random_field((40, 30), "smooth", 1)
+    for rel in (1e-3, 1e-4, 0.25):
+        assert dmt.dmt_xi_from_relative(ctx, _t(g), rel) == synth.xi_from_relative(g, rel)
+
+
+def _compare_correction(ctx, dmt, w, tier=None, q_max=None, max_iters=-1):
+    tier = w.tier if tier is None else tier
+    q_max = w.q_max if q_max is None else q_max
+    nx, ny, nz = w.dims
+    cx = oracle.Complex.grid(nx, ny, nz)
+    o = oracle.correct(cx, w.f.reshape(-1), w.g_hat.reshape(-1), w.xi, tier, q_max,
+                       max_iters=(1 << 40) if max_iters < 0 else max_iters)
+    r = dmt.dmt_correct(ctx, _t(w.f), _t(w.g_hat), w.xi, tier, q_max, max_iters)
+    assert r.status == o["status"]
+    for k, v in o["stats"].items():
+        if k != "status":
+            assert r.stats[k] == v, k
+    assert np.array_equal(r.g.cpu().numpy().reshape(-1).view(np.uint32), o["g"].view(np.uint32))
+    assert np.array_equal(r.q.cpu().numpy().reshape(-1), o["q"])
+    assert np.array_equal(r.lossless_idx.cpu().numpy(), o["lossless_idx"])
+    assert np.array_equal(r.lossless_val.cpu().numpy().view(np.uint32), o["lossless_val"].view(np.uint32))
+    assert np.array_equal(r.log.numpy()[:, :13], o["log"][:, :13])
+    # decoder reproduces the corrected field
+    dec = dmt.dmt_apply_edits(ctx, _t(w.g_hat), r.q, r.lossless_idx, r.lossless_val, w.xi, q_max)
+    assert torch.equal(dec.view(torch.int32), r.g.view(torch.int32))
+    return r, o
+
+
+CORR_CASES = [
+    ((12, 9), "uniform", "noise", 0.2), ((12, 9), "plateau", "bin", 0.2), ((33, 17), "smooth", "noise", 0.05),
+    ((64, 48), "uniform", "bin", 0.01), ((5, 4, 3), "uniform", "noise", 0.2), ((9, 8, 7), "plateau", "bin", 0.1),
+    ((12, 10, 9), "smooth", "noise", 0.02), ((20, 3, 11), "uniform", "bin", 0.05),
+]
+
+
+@pytest.mark.parametrize("shape,kind,ghat,rel", CORR_CASES)
+@pytest.mark.parametrize("tier", [1, 2, 3, 4])
+def test_correct_small(ctx, dmt, shape, kind, ghat, rel, tier):
+    w = synth.tiny_cases(11, shape, rel=rel, kind=kind, ghat=ghat)
+    _compare_correction(ctx, dmt, w, tier=tier)
+
+
+@pytest.mark.parametrize("q_max", [0, 2, 7])
+def test_correct_qmax(ctx, dmt, q_max):
+    w = synth.tiny_cases(4, (24, 21), rel=0.1, kind="uniform", ghat="noise")
+    _compare_correction(ctx, dmt, w, q_max=q_max)
+
+
+@pytest.mark.parametrize("max_iters", [0, 1, 5])
+def test_correct_iteration_cap(ctx, dmt, max_iters):
+    w = synth.tiny_cases(6, (30, 20), rel=0.2, kind="uniform", ghat="noise")
+    r, o = _compare_correction(ctx, dmt, w, max_iters=max_iters)
+    assert r.status == "not_converged" and r.stats["residual_violations"] > 0
+
+
+def test_correct_small2d_config(ctx, dmt):
+    """The 128x128 Gaussian field with 2*xi bins, full MSC (tier 4)."""
+    w = synth.config_small2d()
+    r, o = _compare_correction(ctx, dmt, w)
+    assert r.status == "ok"
+
+
+def _floor_collision_inversions(w, g):
+    """Adjacent vertex pairs that are both at their floor, with equal floors, in the opposite
+    order to f: decrease-only edits can never separate them (fp32 floors f - xi rounded up
+    merge distinct f values where |f - xi| has a larger exponent than f)."""
+    nx, ny, nz = w.dims
+    lo, _ = oracle.bounds(w.f.reshape(-1), w.xi)
+    F, G = w.f.reshape(nz, ny, nx), g.reshape(nz, ny, nx)
+    Lo = lo.reshape(nz, ny, nx)
+    I = np.arange(F.size).reshape(nz, ny, nx)
+    n = 0
+    for dz in (0, 1):
+        for dy in (0, 1):
+            for dx in (0, 1):
+                if dx == dy == dz == 0 or (nz == 1 and dz):
+                    continue
+                a = (slice(0, nz - dz), slice(0, ny - dy), slice(0, nx - dx))
+                b = (slice(dz, nz), slice(dy, ny), slice(dx, nx))
+                pf = (F[a] < F[b]) | ((F[a] == F[b]) & (I[a] < I[b]))
+                pg = (G[a] < G[b]) | ((G[a] == G[b]) & (I[a] < I[b]))
+                n += int(((pf != pg) & (G[a] == Lo[a]) & (G[b] == Lo[b]) & (G[a] == G[b])).sum())
+    return n
+
+
+def test_correct_atoms3d_small(ctx, dmt):
+    """A 40^3 version of the 3D density field (24 atoms, 2*xi bins), full MSC.  Near the 1e-4
+    background the fp32 floors collide, and this input stalls in the oracle and on the GPU alike;
+    the stall must be explained by floor collisions."""
+    w = synth.config_atoms3d(seed=3, side=40, n_atoms=24)
+    r, o = _compare_correction(ctx, dmt, w)
+    if r.status != "ok":
+        assert r.stats["stalled"] == 1 and r.stats["residual_violations"] > 0
+        assert _floor_collision_inversions(w, r.g.cpu().numpy().reshape(-1)) > 0
+
+
+def test_identity_and_errors(ctx, dmt):
+    w = synth.tiny_cases(1, (16, 16), rel=0.1)
+    r = dmt.dmt_correct(ctx, _t(w.f), _t(w.f), w.xi)
+    assert r.status == "ok" and r.stats["iterations"] == 0 and r.stats["n_edited"] == 0
+    f = _t(w.f)
+    with pytest.raises(dmt.DmtError) as e:
+        dmt.dmt_correct(ctx, f, f + 1.0, w.xi)
+    assert e.value.status == -2
+    bad = f.clone()
+    bad[3, 3] = float("nan")
+    with pytest.raises(dmt.DmtError) as e:
+        dmt.dmt_correct(ctx, bad, f, w.xi)
+    assert e.value.status == -3
+    with pytest.raises(dmt.DmtError) as e:
+        dmt.dmt_correct(ctx, f, f, w.xi, tier=7)
+    assert e.value.status == -1
+    with pytest.raises(dmt.DmtError) as e:
+        dmt.dmt_correct(ctx, f[:1], f[:1], w.xi)
+    assert e.value.status == -1
