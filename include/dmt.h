@@ -74,8 +74,16 @@ typedef struct {
     int32_t tier;              /* dmt_tier */
     int32_t q_max;             /* 0..7: edit step xi / 2^q_max (Equation 2); the paper uses 6 */
     int64_t max_iters;         /* cap on edit iterations (C + S); < 0 means no cap */
-    uint32_t flags;            /* reserved, must be 0 */
+    uint32_t flags;            /* 0, or DMT_F_DENSE / DMT_F_PHASES */
 } dmt_options;
+
+/* Option flags (results are bit-identical in every form; they exist for testing):
+ * DMT_F_DENSE   recompute the whole gradient and every violation each iteration instead of only
+ *               around the vertices edited in the previous iteration;
+ * DMT_F_PHASES  run the loop as one kernel launch per phase instead of one persistent
+ *               cooperative kernel. */
+#define DMT_F_DENSE 1u
+#define DMT_F_PHASES 2u
 
 typedef struct {
     int64_t iterations;        /* edit iterations applied (C + S) */
@@ -189,7 +197,12 @@ enum {
     DMT_PROF_SSTEP = 3,     /* separatrix troublemaker pass, units = branch cells */
     DMT_PROF_SETUP = 4,     /* floors and validation, units = vertices */
     DMT_PROF_MSC = 5,       /* critical cells + separatrix branches of f, units = vertices */
-    DMT_PROF_KERNELS = 6
+    DMT_PROF_LOOP = 6,      /* the frontier correction loop (persistent kernel or its phases) */
+    /* phases inside the persistent loop kernel of the last dmt_correct (wall clock of block 0,
+     * including the grid barrier that ends each phase; launches and units read 0): */
+    DMT_PROF_LOOP_GRAD = 7, DMT_PROF_LOOP_VMASK = 8, DMT_PROF_LOOP_REQUESTS = 9,
+    DMT_PROF_LOOP_SCHECK = 10, DMT_PROF_LOOP_STARGETS = 11, DMT_PROF_LOOP_APPLY = 12,
+    DMT_PROF_KERNELS = 13
 };
 
 /* Turns event timing of the kernel families on (1) or off (0) for later calls on ctx and

@@ -60,6 +60,9 @@ struct Geom {
     int tri_index[14][14];
     uint32_t edge_trimask[14];   // apex slots of the star triangles on edge (v, s)
     uint32_t tri_tetmask[36];    // apex slots of the star tetrahedra on triangle (v, s, t)
+    // anchors whose cells contain a vertex of the closed 1-ring of v (offsets from v)
+    int naff;
+    int aff_d[64][3];
 };
 
 template <int D>
@@ -286,6 +289,26 @@ constexpr Geom<D> make_geom() {
             }
         }
     }
+    // affected anchors: d = o - c, o in the closed 1-ring offsets, c in {0,1}^D
+    g.naff = 0;
+    for (int dz = (D == 3 ? -2 : 0); dz <= (D == 3 ? 1 : 0); dz++)
+        for (int dy = -2; dy <= 1; dy++)
+            for (int dx = -2; dx <= 1; dx++) {
+                int hit = 0;
+                for (int s = -1; s < NS; s++) {
+                    int o[3] = {0, 0, 0};
+                    if (s >= 0) for (int k = 0; k < 3; k++) o[k] = g.slot_d[s][k];
+                    for (int cb = 0; cb <= FULL; cb++) {
+                        int c[3] = {0, 0, 0};
+                        bits_to_d<D>(cb, c);
+                        if (o[0] - c[0] == dx && o[1] - c[1] == dy && o[2] - c[2] == dz) hit = 1;
+                    }
+                }
+                if (hit) {
+                    g.aff_d[g.naff][0] = dx; g.aff_d[g.naff][1] = dy; g.aff_d[g.naff][2] = dz;
+                    g.naff++;
+                }
+            }
     for (int i = 0; i < ntet; i++) {
         int s = g.tet_s[i], t = g.tet_t[i], u = g.tet_u[i];
         g.tri_tetmask[g.tri_index[s][t]] |= 1u << u;

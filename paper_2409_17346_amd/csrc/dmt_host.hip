@@ -6,12 +6,13 @@
 #include <cfloat>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
 
 #include "dmt.h"
-#include "dmt_kernels.h"
+#include "dmt_frontier.h"
 
 using namespace dmt;
 
@@ -39,6 +40,9 @@ struct dmt_context {
     int64_t n_desc = 0, n_desc_cells = 0, n_asc = 0, n_asc_cells = 0;
     DevBuf vlab, tlab;
     int64_t n_vlab = 0, n_tlab = 0;
+    // frontier loop state
+    DevBuf ctl, vmask, inlist, vl0, vl1, dvl0, dvl1, dal0, dal1, vstamp, astamp, rstamp, reql, dlog;
+    Ctl* hctl = nullptr;                  // pinned
     bool have_msc = false;
     DevBuf ll_idx, ll_val;
     int64_t n_lossless = 0;
@@ -287,6 +291,164 @@ dmt_status read_counters(dmt_context* c, hipStream_t st) {
     return DMT_OK;
 }
 
+// Frontier loop: the iterations run on the device in batches; the host reads the control block
+// once per batch and grows the log buffer ahead of the next batch.
+template <int D>
+dmt_status frontier_loop(dmt_context* c, const Dims& dm, const float* f, const float* gh, const float* lo, float* g,
+                         uint8_t* state, const uint8_t* fpl, uint8_t* gpl, float delta, const dmt_options* o,
+                         int64_t& it, int64_t& c_it, int64_t& s_it, int64_t& residual, int& converged,
+                         int& stalled, hipStream_t st) {
+    const int n = dm.n;
+    ENSURE(c, c->ctl, sizeof(Ctl));
+    ENSURE(c, c->vmask, sizeof(uint32_t) * n);
+    ENSURE(c, c->inlist, n);
+    ENSURE(c, c->vl0, sizeof(int) * n);
+    ENSURE(c, c->vl1, sizeof(int) * n);
+    ENSURE(c, c->dvl0, sizeof(int) * n);
+    ENSURE(c, c->dvl1, sizeof(int) * n);
+    ENSURE(c, c->dal0, sizeof(int) * n);
+    ENSURE(c, c->dal1, sizeof(int) * n);
+    ENSURE(c, c->vstamp, sizeof(unsigned) * n);
+    ENSURE(c, c->astamp, sizeof(unsigned) * n);
+    ENSURE(c, c->rstamp, sizeof(unsigned) * n);
+    ENSURE(c, c->reql, sizeof(int) * n);
+    HIPCHK(c, hipMemsetAsync(c->inlist.p, 0, n, st));
+    HIPCHK(c, hipMemsetAsync(c->vstamp.p, 0, sizeof(unsigned) * n, st));
+    HIPCHK(c, hipMemsetAsync(c->astamp.p, 0, sizeof(unsigned) * n, st));
+    HIPCHK(c, hipMemsetAsync(c->rstamp.p, 0, sizeof(unsigned) * n, st));
+    k_fr_init<<<1, 1, 0, st>>>(P<Ctl>(c->ctl));
+    CHECK_LAUNCH(c);
+
+    FrontierBufs B{};
+    B.ctl = P<Ctl>(c->ctl);
+    B.f = f; B.gh = gh; B.lo = lo; B.g = g; B.state = state; B.fpl = fpl; B.gpl = gpl;
+    B.vmask = P<uint32_t>(c->vmask);
+    B.inlist = P<uint8_t>(c->inlist);
+    B.vl[0] = P<int>(c->vl0); B.vl[1] = P<int>(c->vl1);
+    B.dvl[0] = P<int>(c->dvl0); B.dvl[1] = P<int>(c->dvl1);
+    B.dal[0] = P<int>(c->dal0); B.dal[1] = P<int>(c->dal1);
+    B.vstamp = P<unsigned>(c->vstamp); B.astamp = P<unsigned>(c->astamp); B.rstamp = P<unsigned>(c->rstamp);
+    B.reql = P<int>(c->reql);
+    if (o->tier >= 3 && c->have_msc) {
+        B.dcell = P<int>(c->dcell); B.dcbr = P<int>(c->dcbr); B.dterm = P<int>(c->dterm);
+        B.acell = P<int>(c->acell); B.acbr = P<int>(c->acbr); B.aterm = P<int>(c->aterm);
+        B.doff = P<int64_t>(c->doff); B.aoff = P<int64_t>(c->aoff);
+        B.dfirst = P<int>(c->dfirst); B.afirst = P<int>(c->afirst);
+        B.n_dcell = c->n_desc_cells; B.n_acell = c->n_asc_cells;
+        B.n_desc = (int)c->n_desc; B.n_asc = (int)c->n_asc;
+    }
+    B.delta = delta;
+    B.q_max = o->q_max;
+    B.tier = o->tier;
+    B.max_iters = o->max_iters < 0 ? INT64_MAX : o->max_iters;
+
+    // Persistent form: one cooperative launch runs the loop with grid barriers; it pauses when
+    // the log buffer is full, and the host grows the buffer and launches it again.
+    size_t log_cap = c->dlog.cap / (sizeof(long long) * DMT_LOG_WORDS);
+    auto grow_log = [&](size_t need, int64_t keep) -> dmt_status {
+        if (need <= log_cap) return DMT_OK;
+        const size_t ncap = need * 2;
+        DevBuf nb;
+        if (hipMalloc(&nb.p, ncap * sizeof(long long) * DMT_LOG_WORDS) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(c, DMT_E_NOMEM, "log allocation failed");
+        }
+        nb.cap = ncap * sizeof(long long) * DMT_LOG_WORDS;
+        if (c->dlog.p && keep > 0)
+            HIPCHK(c, hipMemcpyAsync(nb.p, c->dlog.p, (size_t)keep * sizeof(long long) * DMT_LOG_WORDS,
+                                     hipMemcpyDeviceToDevice, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        if (c->dlog.p) (void)hipFree(c->dlog.p);
+        c->dlog = nb;
+        log_cap = ncap;
+        return DMT_OK;
+    };
+    bool persistent = !(o->flags & DMT_F_PHASES);
+    int coop_blocks = 0;
+    if (persistent) {
+        int ncu = 0, occ = 0, coop = 0;
+        HIPCHK(c, hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, c->device));
+        HIPCHK(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device));
+        HIPCHK(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(k_fr_loop<D>),
+                                                               TPB, 0));
+        // The persistent grid only has to cover the frontier (iteration 0 runs as full-grid launches),
+        // and a grid barrier costs more the more blocks arrive at it, so the grid is small.
+        int want = 32;
+        if (const char* e = getenv("DMT_COOP_BLOCKS")) want = atoi(e) > 0 ? atoi(e) : want;
+        coop_blocks = want < ncu * occ ? want : ncu * occ;
+        persistent = coop && coop_blocks > 0;
+    }
+    int64_t host_it = 0;
+    if (persistent) {
+        const unsigned long long timeout = 500000000ull;   // 5 s of the 100 MHz wall clock
+        {
+            // iteration 0: dense gradient of g and violation masks of every anchor
+            const unsigned gfull = nblocks(n) < 2048u ? nblocks(n) : 2048u;
+            ProfScope ps(c, DMT_PROF_GRADIENT, st, n);
+            k_fr_grad<D><<<gfull, TPB, 0, st>>>(B, dm);
+            k_fr_vmask<D><<<gfull, TPB, 0, st>>>(B, dm);
+            CHECK_LAUNCH(c);
+        }
+        for (;;) {
+            dmt_status gs = grow_log((size_t)host_it + 4096, host_it);
+            if (gs != DMT_OK) return gs;
+            B.log = P<long long>(c->dlog);
+            int cap = (int)(log_cap < (size_t)INT32_MAX ? log_cap : (size_t)INT32_MAX);
+            void* args[] = {&B, (void*)&dm, &cap, (void*)&timeout};
+            {
+                ProfScope ps(c, DMT_PROF_LOOP, st, 0);
+                HIPCHK(c, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_fr_loop<D>), dim3(coop_blocks),
+                                                     dim3(TPB), args, 0, st));
+            }
+            HIPCHK(c, hipMemcpyAsync(c->hctl, c->ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+            HIPCHK(c, hipStreamSynchronize(st));
+            if (c->hctl->err) return fail(c, DMT_E_HIP, "grid barrier timed out in the persistent loop");
+            host_it = c->hctl->it;
+            if (c->hctl->done != 4) break;
+            const int zero = 0;
+            HIPCHK(c, hipMemcpyAsync(&P<Ctl>(c->ctl)->done, &zero, sizeof(int), hipMemcpyHostToDevice, st));
+        }
+    } else {
+        // Launch-per-phase form: batches of iterations without host synchronisation.
+        const unsigned gfull = nblocks(n) < 2048u ? nblocks(n) : 2048u;
+        int batch = 4;
+        for (;;) {
+            dmt_status gs = grow_log((size_t)host_it + (size_t)batch + 1, host_it);
+            if (gs != DMT_OK) return gs;
+            B.log = P<long long>(c->dlog);
+            for (int b = 0; b < batch; b++) {
+                ProfScope ps(c, DMT_PROF_LOOP, st, 0);
+                k_fr_grad<D><<<gfull, TPB, 0, st>>>(B, dm);
+                k_fr_vmask<D><<<gfull, TPB, 0, st>>>(B, dm);
+                k_fr_requests<D><<<gfull, TPB, 0, st>>>(B, dm);
+                if (o->tier >= 3) {
+                    k_fr_scheck<D><<<gfull, TPB, 0, st>>>(B, dm);
+                    k_fr_stargets<D><<<gfull, TPB, 0, st>>>(B, dm);
+                }
+                k_fr_apply<D><<<gfull, TPB, 0, st>>>(B, dm);
+                k_fr_finish<<<1, 1, 0, st>>>(B);
+                CHECK_LAUNCH(c);
+            }
+            HIPCHK(c, hipMemcpyAsync(c->hctl, c->ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+            HIPCHK(c, hipStreamSynchronize(st));
+            host_it = c->hctl->it;
+            if (c->hctl->done) break;
+            if (batch < 256) batch *= 2;
+        }
+    }
+    it = c->hctl->it;
+    c_it = c->hctl->c_it;
+    s_it = c->hctl->s_it;
+    residual = c->hctl->residual;
+    converged = c->hctl->done == 1;
+    stalled = c->hctl->done == 3;
+    c->log.assign((size_t)it * DMT_LOG_WORDS, 0);
+    if (it > 0)
+        HIPCHK(c, hipMemcpy(c->log.data(), c->dlog.p, sizeof(long long) * DMT_LOG_WORDS * (size_t)it,
+                            hipMemcpyDeviceToHost));
+    return DMT_OK;
+}
+
 template <int D>
 dmt_status correct_impl(dmt_context* c, const Dims& dm, const float* f, const float* gh, float xi,
                         const dmt_options* o, float* g_out, uint8_t* q_out, dmt_stats* stats, hipStream_t st) {
@@ -339,7 +501,12 @@ dmt_status correct_impl(dmt_context* c, const Dims& dm, const float* f, const fl
     int64_t it = 0, c_it = 0, s_it = 0, residual = 0;
     int converged = 0, stalled = 0;
     const int64_t max_iters = o->max_iters < 0 ? INT64_MAX : o->max_iters;
-    for (;;) {
+    if (!(o->flags & DMT_F_DENSE)) {
+        s = frontier_loop<D>(c, dm, f, gh, lo, g, state, fpl, gpl, delta, o, it, c_it, s_it, residual, converged,
+                             stalled, st);
+        if (s != DMT_OK) return s;
+    }
+    for (; o->flags & DMT_F_DENSE;) {
         s = launch_grad(c, D, g, gpl, dm, st);
         if (s != DMT_OK) return s;
         HIPCHK(c, hipMemsetAsync(cnt, 0, sizeof(unsigned long long) * CNT_WORDS, st));
@@ -445,6 +612,7 @@ dmt_status dmt_context_create(dmt_context** ctx, int hip_device) {
     dmt_context* c = new dmt_context();
     c->device = hip_device;
     if (hipHostMalloc((void**)&c->hcnt, sizeof(unsigned long long) * CNT_WORDS, 0) != hipSuccess ||
+        hipHostMalloc((void**)&c->hctl, sizeof(Ctl), 0) != hipSuccess ||
         hipHostMalloc((void**)&c->hscratch, sizeof(int64_t) * 64, 0) != hipSuccess) {
         delete c;
         return DMT_E_NOMEM;
@@ -460,11 +628,13 @@ dmt_status dmt_context_destroy(dmt_context* c) {
                       &c->blkoff, &c->crit[0], &c->crit[1], &c->crit[2], &c->crit[3], &c->dsad, &c->doff, &c->dcell,
                       &c->dcbr, &c->dterm, &c->dlen, &c->dfirst, &c->asad, &c->aoff, &c->acell, &c->acbr, &c->aterm,
                       &c->alen, &c->afirst, &c->astart, &c->asadcnt, &c->asadoff, &c->vlab, &c->tlab, &c->ll_idx,
-                      &c->ll_val};
+                      &c->ll_val, &c->ctl, &c->vmask, &c->inlist, &c->vl0, &c->vl1, &c->dvl0, &c->dvl1, &c->dal0,
+                      &c->dal1, &c->vstamp, &c->astamp, &c->rstamp, &c->reql, &c->dlog};
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     if (c->hcnt) (void)hipHostFree(c->hcnt);
+    if (c->hctl) (void)hipHostFree(c->hctl);
     if (c->hscratch) (void)hipHostFree(c->hscratch);
     delete c;
     return DMT_OK;
@@ -617,7 +787,7 @@ dmt_status dmt_correct(dmt_context* c, const dmt_grid* gr, const float* f, const
     if (s != DMT_OK) return s;
     if (o->tier < 1 || o->tier > 4) return fail(c, DMT_E_INVALID, "tier must be 1..4");
     if (o->q_max < 0 || o->q_max > 7) return fail(c, DMT_E_INVALID, "q_max must be 0..7");
-    if (o->flags != 0) return fail(c, DMT_E_INVALID, "flags must be 0");
+    if (o->flags & ~(uint32_t)(DMT_F_DENSE | DMT_F_PHASES)) return fail(c, DMT_E_INVALID, "unknown flags");
     if (!(xi > 0.0f) || !std::isfinite(xi)) return fail(c, DMT_E_INVALID, "xi must be finite and > 0");
     if (!(ldexpf(xi, -o->q_max) >= FLT_MIN)) return fail(c, DMT_E_INVALID, "xi / 2^q_max is not a normal float");
     HIPCHK(c, hipSetDevice(c->device));
@@ -675,6 +845,12 @@ dmt_status dmt_profile_read(dmt_context* c, int kernel, int64_t* launches, doubl
     *launches = (int64_t)c->prof_ev[kernel].size();
     *ms_total = ms;
     *units = c->prof_units[kernel];
+    if (kernel >= DMT_PROF_LOOP_GRAD && kernel <= DMT_PROF_LOOP_APPLY) {
+        // phases inside the persistent loop: wall-clock ticks (100 MHz) recorded by the kernel
+        *launches = 0;
+        *units = 0;
+        *ms_total = c->ctl.p ? (double)c->hctl->ph[kernel - DMT_PROF_LOOP_GRAD] * 1e-5 : 0.0;
+    }
     return DMT_OK;
 }
 

@@ -202,13 +202,12 @@ __global__ void __launch_bounds__(256) k_minmax(const float* __restrict__ f, int
 // Codes are scattered into the planes at the cells' anchors.
 
 template <int D>
-__global__ void __launch_bounds__(256) k_grad(const float* __restrict__ h, uint8_t* __restrict__ planes, Dims dm) {
+__device__ __forceinline__ void grad_vertex(const int v, const float* __restrict__ h, uint8_t* __restrict__ planes,
+                                            const Dims& dm) {
     constexpr auto& g = G<D>::g;
     constexpr int NS = Geom<D>::NS;
     constexpr int FULL = Geom<D>::FULL;
     constexpr int NTRI = Geom<D>::NTRI;
-    const int v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= dm.n) return;
     int x, y, z;
     coords(dm, v, x, y, z);
     const float hv = h[v];
@@ -328,6 +327,12 @@ __global__ void __launch_bounds__(256) k_grad(const float* __restrict__ h, uint8
             planes[(size_t)g.tet_plane[i] * dm.n + anchor_lin(as)] = code;
         }
     }
+}
+
+template <int D>
+__global__ void __launch_bounds__(256) k_grad(const float* __restrict__ h, uint8_t* __restrict__ planes, Dims dm) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < dm.n) grad_vertex<D>(v, h, planes, dm);
 }
 
 // ----------------------------------------------------------------------------------------

@@ -41,7 +41,9 @@ ABI_SYMBOLS = [
     "dmt_profile_read",
 ]
 
-PROF_KERNELS = {"gradient": 0, "classify": 1, "apply": 2, "sstep": 3, "setup": 4, "msc": 5}
+PROF_KERNELS = {"gradient": 0, "classify": 1, "apply": 2, "sstep": 3, "setup": 4, "msc": 5, "loop": 6,
+                "loop.grad": 7, "loop.vmask": 8, "loop.requests": 9, "loop.scheck": 10, "loop.stargets": 11,
+                "loop.apply": 12}
 
 
 class DmtError(RuntimeError):
@@ -224,9 +226,13 @@ class Result:
     log: torch.Tensor
 
 
+DMT_F_DENSE = 1
+DMT_F_PHASES = 2
+
+
 def dmt_correct(ctx: Context, f: torch.Tensor, g_hat: torch.Tensor, xi: float, tier: int = 4, q_max: int = 6,
                 max_iters: int = -1, want_edits: bool = True, g_out: torch.Tensor | None = None,
-                q_out: torch.Tensor | None = None) -> Result:
+                q_out: torch.Tensor | None = None, flags: int = 0) -> Result:
     _dev(f)
     _dev(g_hat)
     if f.shape != g_hat.shape:
@@ -234,7 +240,7 @@ def dmt_correct(ctx: Context, f: torch.Tensor, g_hat: torch.Tensor, xi: float, t
     g_out = torch.empty_like(f) if g_out is None else g_out
     q_out = torch.empty(f.shape, dtype=torch.uint8, device=f.device) if q_out is None else q_out
     st = dmt_stats()
-    opts = dmt_options(tier, q_max, max_iters, 0)
+    opts = dmt_options(tier, q_max, max_iters, flags)
     g = grid_of(f)
     rc = ctx.check(ctx.L.dmt_correct(ctx.h, C.byref(g), VP(f.data_ptr()), VP(g_hat.data_ptr()), xi, C.byref(opts),
                                      VP(g_out.data_ptr()), VP(q_out.data_ptr()), C.byref(st), _stream(f)),

@@ -86,14 +86,14 @@ def test_bounds_and_xi(ctx, dmt):
         assert dmt.dmt_xi_from_relative(ctx, _t(g), rel) == synth.xi_from_relative(g, rel)
 
 
-def _compare_correction(ctx, dmt, w, tier=None, q_max=None, max_iters=-1):
+def _compare_correction(ctx, dmt, w, tier=None, q_max=None, max_iters=-1, flags=0):
     tier = w.tier if tier is None else tier
     q_max = w.q_max if q_max is None else q_max
     nx, ny, nz = w.dims
     cx = oracle.Complex.grid(nx, ny, nz)
     o = oracle.correct(cx, w.f.reshape(-1), w.g_hat.reshape(-1), w.xi, tier, q_max,
                        max_iters=(1 << 40) if max_iters < 0 else max_iters)
-    r = dmt.dmt_correct(ctx, _t(w.f), _t(w.g_hat), w.xi, tier, q_max, max_iters)
+    r = dmt.dmt_correct(ctx, _t(w.f), _t(w.g_hat), w.xi, tier, q_max, max_iters, flags=flags)
     assert r.status == o["status"]
     for k, v in o["stats"].items():
         if k != "status":
@@ -116,11 +116,15 @@ CORR_CASES = [
 ]
 
 
+FORMS = pytest.mark.parametrize("flags", [0, 1, 2], ids=["persistent", "dense", "phases"])
+
+
 @pytest.mark.parametrize("shape,kind,ghat,rel", CORR_CASES)
 @pytest.mark.parametrize("tier", [1, 2, 3, 4])
-def test_correct_small(ctx, dmt, shape, kind, ghat, rel, tier):
+@FORMS
+def test_correct_small(ctx, dmt, shape, kind, ghat, rel, tier, flags):
     w = synth.tiny_cases(11, shape, rel=rel, kind=kind, ghat=ghat)
-    _compare_correction(ctx, dmt, w, tier=tier)
+    _compare_correction(ctx, dmt, w, tier=tier, flags=flags)
 
 
 @pytest.mark.parametrize("q_max", [0, 2, 7])
@@ -129,18 +133,30 @@ def test_correct_qmax(ctx, dmt, q_max):
     _compare_correction(ctx, dmt, w, q_max=q_max)
 
 
-@pytest.mark.parametrize("max_iters", [0, 1, 5])
-def test_correct_iteration_cap(ctx, dmt, max_iters):
+@pytest.mark.parametrize("max_iters", [0, 1, 5, 37])
+@FORMS
+def test_correct_iteration_cap(ctx, dmt, max_iters, flags):
     w = synth.tiny_cases(6, (30, 20), rel=0.2, kind="uniform", ghat="noise")
-    r, o = _compare_correction(ctx, dmt, w, max_iters=max_iters)
+    r, o = _compare_correction(ctx, dmt, w, max_iters=max_iters, flags=flags)
     assert r.status == "not_converged" and r.stats["residual_violations"] > 0
 
 
-def test_correct_small2d_config(ctx, dmt):
+@FORMS
+def test_correct_small2d_config(ctx, dmt, flags):
     """The 128x128 Gaussian field with 2*xi bins, full MSC (tier 4)."""
     w = synth.config_small2d()
-    r, o = _compare_correction(ctx, dmt, w)
+    r, o = _compare_correction(ctx, dmt, w, flags=flags)
     assert r.status == "ok"
+
+
+@pytest.mark.parametrize("flags", [0, 2], ids=["persistent", "phases"])
+def test_correct_large2d_crop(ctx, dmt, flags):
+    """A 256x256 corner of the 2048^2 workload (hundreds of C and S iterations)."""
+    w = synth.config_large2d()
+    w.f = np.ascontiguousarray(w.f[:256, :256])
+    w.g_hat = np.ascontiguousarray(w.g_hat[:256, :256])
+    r, o = _compare_correction(ctx, dmt, w, flags=flags)
+    assert r.status == "ok" and r.stats["s_iterations"] > 100
 
 
 def _floor_collision_inversions(w, g):
