@@ -172,6 +172,29 @@ dmt_status dmt_correct(dmt_context *ctx, const dmt_grid *grid, const float *f, c
                        float xi, const dmt_options *opts, float *g_out, uint8_t *q_out,
                        dmt_stats *stats_host, hipStream_t stream);
 
+/* One job of a batch (Section 5.7: every field of a time series is corrected on its own).
+ * Inputs: grid, device pointers f and g_hat, xi, options (flags must be 0), output device
+ * pointers g_out and q_out, as for dmt_correct.  Filled by the call: status and stats. */
+typedef struct {
+    dmt_grid grid;
+    const float *f, *g_hat;
+    float xi;
+    dmt_options opts;
+    float *g_out;
+    uint8_t *q_out;
+    dmt_status status;
+    dmt_stats stats;
+} dmt_job;
+
+/* Corrects n_jobs independent fields of any sizes (2D and 3D mixed) together: their C/S loops
+ * run in lockstep inside one persistent kernel, so each grid-wide synchronisation serves every
+ * unfinished field.  Every job's outputs equal those of dmt_correct on the same inputs.  A job
+ * that fails validation gets its error status and is skipped; the others still run.  Returns
+ * the first job error, else DMT_W_NOT_CONVERGED if any job did not converge, else DMT_OK.  The
+ * lossless edits of a job are the vertices whose q_out is 0xFF, with values g_out; no
+ * per-iteration log is kept. */
+dmt_status dmt_correct_batch(dmt_context *ctx, int32_t n_jobs, dmt_job *jobs_host, hipStream_t stream);
+
 /* Lossless edits of the last dmt_correct: vertex ids ascending and their final values.
  * Writes min(count, cap) entries, returns the full count in count_host. */
 dmt_status dmt_lossless_edits(dmt_context *ctx, int64_t *idx_out, float *val_out, int64_t cap,
@@ -199,10 +222,10 @@ enum {
     DMT_PROF_MSC = 5,       /* critical cells + separatrix branches of f, units = vertices */
     DMT_PROF_LOOP = 6,      /* the frontier correction loop (persistent kernel or its phases) */
     /* phases inside the persistent loop kernel of the last dmt_correct (wall clock of block 0,
-     * including the grid barrier that ends each phase; launches and units read 0): */
-    DMT_PROF_LOOP_GRAD = 7, DMT_PROF_LOOP_VMASK = 8, DMT_PROF_LOOP_REQUESTS = 9,
-    DMT_PROF_LOOP_SCHECK = 10, DMT_PROF_LOOP_STARGETS = 11, DMT_PROF_LOOP_APPLY = 12,
-    DMT_PROF_KERNELS = 13
+     * including the grid barrier that ends each phase; launches and units read 0): the
+     * troublemaker pass, the gradient pass and the violation pass */
+    DMT_PROF_LOOP_SAPPLY = 7, DMT_PROF_LOOP_GRAD = 8, DMT_PROF_LOOP_VR = 9,
+    DMT_PROF_KERNELS = 10
 };
 
 /* Turns event timing of the kernel families on (1) or off (0) for later calls on ctx and

@@ -1,6 +1,7 @@
-// Host side of the C ABI declared in include/dmt.h: validation, workspace, MSC extraction and
-// the C-loop / S-loop driver (Sections 4.2-4.6 of the paper).  All arithmetic on field values
-// happens in the kernels of dmt_kernels.h; the host only sequences launches and reads counters.
+// Host side of the C ABI declared in include/dmt.h: validation, workspaces, MSC extraction and
+// the driver of the C-loop / S-loop correction (Sections 4.2-4.6 of the paper).  All arithmetic
+// on field values happens in the kernels of dmt_kernels.h and dmt_frontier.h; the host only
+// sequences launches, sizes buffers and reads counters.
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
@@ -26,29 +27,47 @@ struct DevBuf {
 constexpr int TPB = 256;
 inline unsigned nblocks(int64_t n) { return (unsigned)((n + TPB - 1) / TPB); }
 
+// Critical cells and separatrix branches of one gradient (device arrays, int32 ids).
+struct MscBufs {
+    DevBuf crit[4];
+    int64_t ncrit[4] = {0, 0, 0, 0};
+    DevBuf dlen, dterm, doff, dfirst, dcell, dcbr;
+    DevBuf asadcnt, asadoff, astart, asad, alen, aterm, aoff, afirst, acell, acbr;
+    DevBuf vlab, tlab;
+    int64_t n_desc = 0, n_desc_cells = 0, n_asc = 0, n_asc_cells = 0, n_vlab = 0, n_tlab = 0;
+    bool valid = false;
+    std::vector<DevBuf*> all() {
+        return {&crit[0], &crit[1], &crit[2], &crit[3], &dlen, &dterm, &doff, &dfirst, &dcell, &dcbr, &asadcnt,
+                &asadoff, &astart, &asad, &alen, &aterm, &aoff, &afirst, &acell, &acbr, &vlab, &tlab};
+    }
+};
+
+// Device state of one correction job.
+struct JobWs {
+    DevBuf lo, g0, g1, state, fpl, gpl, vmask, vl0, vl1, dvl0, dvl1, dal0, dal1, vstamp, astamp, astamp1, rstamp, ctl;
+    MscBufs msc;
+    std::vector<DevBuf*> all() {
+        std::vector<DevBuf*> v = {&lo, &g0, &g1, &state, &fpl, &gpl, &vmask, &vl0, &vl1, &dvl0, &dvl1, &dal0, &dal1,
+                                  &vstamp, &astamp, &astamp1, &rstamp, &ctl};
+        for (DevBuf* b : msc.all()) v.push_back(b);
+        return v;
+    }
+};
+
 }  // namespace
 
 struct dmt_context {
     int device = 0;
     std::string err;
-    DevBuf lo, g, state, req, fpl, gpl, cnt, flags, part, blk, blkoff;
-    DevBuf crit[4];
-    int64_t ncrit[4] = {0, 0, 0, 0};
-    // descending / ascending branches (int32 cell ids, int64 offsets)
-    DevBuf dsad, doff, dcell, dcbr, dterm, dlen, dfirst;
-    DevBuf asad, aoff, acell, acbr, aterm, alen, afirst, astart, asadcnt, asadoff;
-    int64_t n_desc = 0, n_desc_cells = 0, n_asc = 0, n_asc_cells = 0;
-    DevBuf vlab, tlab;
-    int64_t n_vlab = 0, n_tlab = 0;
-    // frontier loop state
-    DevBuf ctl, vmask, inlist, vl0, vl1, dvl0, dvl1, dal0, dal1, vstamp, astamp, rstamp, reql, dlog;
-    Ctl* hctl = nullptr;                  // pinned
-    bool have_msc = false;
-    DevBuf ll_idx, ll_val;
+    std::vector<JobWs> ws;                 // one workspace per job of the last batch (ws[0]: single calls)
+    MscBufs msc;                           // results of dmt_extract_msc
+    DevBuf gpl, req, cnt, flags, part, blk, blkoff, ll_idx, ll_val, dlog, jobs_dev, dims_dev, run_dev, bctl;
     int64_t n_lossless = 0;
     std::vector<int64_t> log;
-    unsigned long long* hcnt = nullptr;   // pinned
-    int64_t* hscratch = nullptr;          // pinned
+    unsigned long long* hcnt = nullptr;    // pinned
+    int64_t* hscratch = nullptr;           // pinned
+    BatchCtl* hbctl = nullptr;             // pinned
+    std::vector<Ctl> hctl;                 // per-job control blocks read back after the loop
     // kernel timing: event pairs per kernel family, recorded on the launch stream
     bool prof = false;
     std::vector<hipEvent_t> ev_pool;
@@ -93,6 +112,12 @@ dmt_status ensure(dmt_context* c, DevBuf& b, size_t bytes) {
         if (s_ != DMT_OK) return s_;                   \
     } while (0)
 
+#define TRY(expr)                         \
+    do {                                  \
+        dmt_status s_ = (expr);           \
+        if (s_ != DMT_OK) return s_;      \
+    } while (0)
+
 template <typename T>
 T* P(DevBuf& b) { return reinterpret_cast<T*>(b.p); }
 
@@ -115,6 +140,16 @@ dmt_status check_grid(dmt_context* c, const dmt_grid* gr, Dims& dm, int& D) {
     return DMT_OK;
 }
 
+dmt_status check_options(dmt_context* c, const dmt_options* o, float xi) {
+    if (!o) return fail(c, DMT_E_INVALID, "options are NULL");
+    if (o->tier < 1 || o->tier > 4) return fail(c, DMT_E_INVALID, "tier must be 1..4");
+    if (o->q_max < 0 || o->q_max > 7) return fail(c, DMT_E_INVALID, "q_max must be 0..7");
+    if (o->flags & ~(uint32_t)(DMT_F_DENSE | DMT_F_PHASES)) return fail(c, DMT_E_INVALID, "unknown flags");
+    if (!(xi > 0.0f) || !std::isfinite(xi)) return fail(c, DMT_E_INVALID, "xi must be finite and > 0");
+    if (!(ldexpf(xi, -o->q_max) >= FLT_MIN)) return fail(c, DMT_E_INVALID, "xi / 2^q_max is not a normal float");
+    return DMT_OK;
+}
+
 int nplanes(int D) { return D == 2 ? Geom<2>::NB : Geom<3>::NB; }
 int ntypes(int D, int d) { return D == 2 ? G<2>::g.ntypes[d] : G<3>::g.ntypes[d]; }
 
@@ -127,7 +162,7 @@ hipEvent_t next_event(dmt_context* c) {
     return c->ev_pool[c->ev_used++];
 }
 
-// Brackets one launch of kernel family k with events when timing is on.
+// Brackets the launches of kernel family k with events when timing is on.
 struct ProfScope {
     dmt_context* c;
     int k;
@@ -156,7 +191,7 @@ dmt_status launch_grad(dmt_context* c, int D, const float* h, uint8_t* pl, const
     return DMT_OK;
 }
 
-// exclusive scan of n ints into n+1 int64 (device), total returned on the host
+// exclusive scan of n ints into n+1 int64 (device); the total is returned on the host
 dmt_status scan(dmt_context* c, const int* in, int64_t n, int64_t* out, int64_t* total, hipStream_t st) {
     k_scan_single<<<1, 1024, 0, st>>>(in, n, out);
     CHECK_LAUNCH(c);
@@ -174,11 +209,13 @@ dmt_status fill_i32(dmt_context* c, int* p, int64_t n, int value, hipStream_t st
     return DMT_OK;
 }
 
-// Critical cells and separatrix branches of the gradient in planes pl (Section 3.1).
+// Critical cells, separatrix branches and (optionally) manifold labels of the gradient in
+// planes pl (Section 3.1).
 template <int D>
-dmt_status build_msc(dmt_context* c, const uint8_t* pl, const Dims& dm, bool labels, hipStream_t st) {
+dmt_status build_msc(dmt_context* c, MscBufs& m, const uint8_t* pl, const Dims& dm, bool labels, hipStream_t st) {
     constexpr auto& g = G<D>::g;
     const unsigned nb = nblocks(dm.n);
+    m.valid = false;
     ENSURE(c, c->flags, 16);
     HIPCHK(c, hipMemsetAsync(c->flags.p, 0, sizeof(unsigned), st));
     unsigned* werr = P<unsigned>(c->flags);
@@ -187,101 +224,94 @@ dmt_status build_msc(dmt_context* c, const uint8_t* pl, const Dims& dm, bool lab
     k_crit_count<D><<<nb, TPB, 0, st>>>(pl, dm, P<int>(c->blk));
     CHECK_LAUNCH(c);
     for (int d = 0; d <= D; d++) {
-        dmt_status s = scan(c, P<int>(c->blk) + (size_t)d * nb, nb, P<int64_t>(c->blkoff) + (size_t)d * (nb + 1),
-                            &c->ncrit[d], st);
-        if (s != DMT_OK) return s;
-        ENSURE(c, c->crit[d], sizeof(int) * (size_t)c->ncrit[d]);
+        TRY(scan(c, P<int>(c->blk) + (size_t)d * nb, nb, P<int64_t>(c->blkoff) + (size_t)d * (nb + 1), &m.ncrit[d],
+                 st));
+        ENSURE(c, m.crit[d], sizeof(int) * (size_t)m.ncrit[d]);
     }
-    for (int d = D + 1; d < 4; d++) c->ncrit[d] = 0;
-    k_crit_write<D><<<nb, TPB, 0, st>>>(pl, dm, P<int64_t>(c->blkoff), (int)nb, P<int>(c->crit[0]),
-                                        P<int>(c->crit[1]), P<int>(c->crit[2]), D == 3 ? P<int>(c->crit[3]) : nullptr);
+    for (int d = D + 1; d < 4; d++) m.ncrit[d] = 0;
+    k_crit_write<D><<<nb, TPB, 0, st>>>(pl, dm, P<int64_t>(c->blkoff), (int)nb, P<int>(m.crit[0]), P<int>(m.crit[1]),
+                                        P<int>(m.crit[2]), D == 3 ? P<int>(m.crit[3]) : nullptr);
     CHECK_LAUNCH(c);
 
     // descending branches: two per 1-saddle
-    c->n_desc = 2 * c->ncrit[1];
-    ENSURE(c, c->dlen, sizeof(int) * (size_t)c->n_desc);
-    ENSURE(c, c->dterm, sizeof(int) * (size_t)c->n_desc);
-    ENSURE(c, c->doff, sizeof(int64_t) * (size_t)(c->n_desc + 1));
-    ENSURE(c, c->dfirst, sizeof(int) * (size_t)c->n_desc);
-    if (c->n_desc) {
-        k_desc_walk<D><<<nblocks(c->n_desc), TPB, 0, st>>>(pl, dm, P<int>(c->crit[1]), (int)c->n_desc, 0,
-                                                           P<int>(c->dlen), P<int>(c->dterm), nullptr, nullptr, nullptr, werr);
+    m.n_desc = 2 * m.ncrit[1];
+    ENSURE(c, m.dlen, sizeof(int) * (size_t)m.n_desc);
+    ENSURE(c, m.dterm, sizeof(int) * (size_t)m.n_desc);
+    ENSURE(c, m.doff, sizeof(int64_t) * (size_t)(m.n_desc + 1));
+    ENSURE(c, m.dfirst, sizeof(int) * (size_t)m.n_desc);
+    if (m.n_desc) {
+        k_desc_walk<D><<<nblocks(m.n_desc), TPB, 0, st>>>(pl, dm, P<int>(m.crit[1]), (int)m.n_desc, 0, P<int>(m.dlen),
+                                                          P<int>(m.dterm), nullptr, nullptr, nullptr, werr);
         CHECK_LAUNCH(c);
     }
-    dmt_status s = scan(c, P<int>(c->dlen), c->n_desc, P<int64_t>(c->doff), &c->n_desc_cells, st);
-    if (s != DMT_OK) return s;
-    ENSURE(c, c->dcell, sizeof(int) * (size_t)c->n_desc_cells);
-    ENSURE(c, c->dcbr, sizeof(int) * (size_t)c->n_desc_cells);
-    if (c->n_desc) {
-        k_desc_walk<D><<<nblocks(c->n_desc), TPB, 0, st>>>(pl, dm, P<int>(c->crit[1]), (int)c->n_desc, 1, nullptr,
-                                                           nullptr, P<int64_t>(c->doff), P<int>(c->dcell), P<int>(c->dcbr), werr);
+    TRY(scan(c, P<int>(m.dlen), m.n_desc, P<int64_t>(m.doff), &m.n_desc_cells, st));
+    ENSURE(c, m.dcell, sizeof(int) * (size_t)m.n_desc_cells);
+    ENSURE(c, m.dcbr, sizeof(int) * (size_t)m.n_desc_cells);
+    if (m.n_desc) {
+        k_desc_walk<D><<<nblocks(m.n_desc), TPB, 0, st>>>(pl, dm, P<int>(m.crit[1]), (int)m.n_desc, 1, nullptr, nullptr,
+                                                          P<int64_t>(m.doff), P<int>(m.dcell), P<int>(m.dcbr), werr);
         CHECK_LAUNCH(c);
     }
-    s = fill_i32(c, P<int>(c->dfirst), c->n_desc, INF32, st);
-    if (s != DMT_OK) return s;
+    TRY(fill_i32(c, P<int>(m.dfirst), m.n_desc, INF32, st));
 
     // ascending branches: one per top cofacet of each (D-1)-saddle
-    const int64_t nsad = c->ncrit[D - 1];
-    ENSURE(c, c->asadcnt, sizeof(int) * (size_t)nsad);
-    ENSURE(c, c->asadoff, sizeof(int64_t) * (size_t)(nsad + 1));
+    const int64_t nsad = m.ncrit[D - 1];
+    ENSURE(c, m.asadcnt, sizeof(int) * (size_t)nsad);
+    ENSURE(c, m.asadoff, sizeof(int64_t) * (size_t)(nsad + 1));
     if (nsad) {
-        k_asc_starts<D><<<nblocks(nsad), TPB, 0, st>>>(dm, P<int>(c->crit[D - 1]), (int)nsad, 0, P<int>(c->asadcnt),
+        k_asc_starts<D><<<nblocks(nsad), TPB, 0, st>>>(dm, P<int>(m.crit[D - 1]), (int)nsad, 0, P<int>(m.asadcnt),
                                                        nullptr, nullptr, nullptr);
         CHECK_LAUNCH(c);
     }
-    s = scan(c, P<int>(c->asadcnt), nsad, P<int64_t>(c->asadoff), &c->n_asc, st);
-    if (s != DMT_OK) return s;
-    ENSURE(c, c->astart, sizeof(int) * (size_t)c->n_asc);
-    ENSURE(c, c->asad, sizeof(int) * (size_t)c->n_asc);
-    ENSURE(c, c->alen, sizeof(int) * (size_t)c->n_asc);
-    ENSURE(c, c->aterm, sizeof(int) * (size_t)c->n_asc);
-    ENSURE(c, c->aoff, sizeof(int64_t) * (size_t)(c->n_asc + 1));
-    ENSURE(c, c->afirst, sizeof(int) * (size_t)c->n_asc);
+    TRY(scan(c, P<int>(m.asadcnt), nsad, P<int64_t>(m.asadoff), &m.n_asc, st));
+    ENSURE(c, m.astart, sizeof(int) * (size_t)m.n_asc);
+    ENSURE(c, m.asad, sizeof(int) * (size_t)m.n_asc);
+    ENSURE(c, m.alen, sizeof(int) * (size_t)m.n_asc);
+    ENSURE(c, m.aterm, sizeof(int) * (size_t)m.n_asc);
+    ENSURE(c, m.aoff, sizeof(int64_t) * (size_t)(m.n_asc + 1));
+    ENSURE(c, m.afirst, sizeof(int) * (size_t)m.n_asc);
     if (nsad) {
-        k_asc_starts<D><<<nblocks(nsad), TPB, 0, st>>>(dm, P<int>(c->crit[D - 1]), (int)nsad, 1, nullptr,
-                                                       P<int64_t>(c->asadoff), P<int>(c->astart), P<int>(c->asad));
+        k_asc_starts<D><<<nblocks(nsad), TPB, 0, st>>>(dm, P<int>(m.crit[D - 1]), (int)nsad, 1, nullptr,
+                                                       P<int64_t>(m.asadoff), P<int>(m.astart), P<int>(m.asad));
         CHECK_LAUNCH(c);
     }
-    if (c->n_asc) {
-        k_asc_walk<D><<<nblocks(c->n_asc), TPB, 0, st>>>(pl, dm, P<int>(c->astart), (int)c->n_asc, 0, P<int>(c->alen),
-                                                         P<int>(c->aterm), nullptr, nullptr, nullptr, werr);
+    if (m.n_asc) {
+        k_asc_walk<D><<<nblocks(m.n_asc), TPB, 0, st>>>(pl, dm, P<int>(m.astart), (int)m.n_asc, 0, P<int>(m.alen),
+                                                        P<int>(m.aterm), nullptr, nullptr, nullptr, werr);
         CHECK_LAUNCH(c);
     }
-    s = scan(c, P<int>(c->alen), c->n_asc, P<int64_t>(c->aoff), &c->n_asc_cells, st);
-    if (s != DMT_OK) return s;
-    ENSURE(c, c->acell, sizeof(int) * (size_t)c->n_asc_cells);
-    ENSURE(c, c->acbr, sizeof(int) * (size_t)c->n_asc_cells);
-    if (c->n_asc) {
-        k_asc_walk<D><<<nblocks(c->n_asc), TPB, 0, st>>>(pl, dm, P<int>(c->astart), (int)c->n_asc, 1, nullptr, nullptr,
-                                                         P<int64_t>(c->aoff), P<int>(c->acell), P<int>(c->acbr), werr);
+    TRY(scan(c, P<int>(m.alen), m.n_asc, P<int64_t>(m.aoff), &m.n_asc_cells, st));
+    ENSURE(c, m.acell, sizeof(int) * (size_t)m.n_asc_cells);
+    ENSURE(c, m.acbr, sizeof(int) * (size_t)m.n_asc_cells);
+    if (m.n_asc) {
+        k_asc_walk<D><<<nblocks(m.n_asc), TPB, 0, st>>>(pl, dm, P<int>(m.astart), (int)m.n_asc, 1, nullptr, nullptr,
+                                                        P<int64_t>(m.aoff), P<int>(m.acell), P<int>(m.acbr), werr);
         CHECK_LAUNCH(c);
     }
-    s = fill_i32(c, P<int>(c->afirst), c->n_asc, INF32, st);
-    if (s != DMT_OK) return s;
-
+    TRY(fill_i32(c, P<int>(m.afirst), m.n_asc, INF32, st));
     HIPCHK(c, hipMemcpyAsync(c->hscratch, werr, sizeof(unsigned), hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));
     if (*reinterpret_cast<unsigned*>(c->hscratch)) return fail(c, DMT_E_HIP, "internal error: a V-path did not end");
-    c->n_vlab = c->n_tlab = 0;
+
+    m.n_vlab = m.n_tlab = 0;
     if (labels) {
-        c->n_vlab = dm.n;
-        c->n_tlab = (int64_t)dm.n * g.ntypes[D];
-        ENSURE(c, c->vlab, sizeof(int) * (size_t)c->n_vlab);
-        ENSURE(c, c->tlab, sizeof(int) * (size_t)c->n_tlab);
-        ENSURE(c, c->flags, 16);
-        k_label_init<D><<<nb, TPB, 0, st>>>(pl, dm, P<int>(c->vlab), P<int>(c->tlab));
+        m.n_vlab = dm.n;
+        m.n_tlab = (int64_t)dm.n * g.ntypes[D];
+        ENSURE(c, m.vlab, sizeof(int) * (size_t)m.n_vlab);
+        ENSURE(c, m.tlab, sizeof(int) * (size_t)m.n_tlab);
+        k_label_init<D><<<nb, TPB, 0, st>>>(pl, dm, P<int>(m.vlab), P<int>(m.tlab));
         CHECK_LAUNCH(c);
         for (int round = 0; round < 64; round++) {
             HIPCHK(c, hipMemsetAsync(c->flags.p, 0, sizeof(unsigned), st));
-            k_jump<<<nblocks(c->n_vlab), TPB, 0, st>>>(P<int>(c->vlab), c->n_vlab, P<unsigned>(c->flags));
-            k_jump<<<nblocks(c->n_tlab), TPB, 0, st>>>(P<int>(c->tlab), c->n_tlab, P<unsigned>(c->flags));
+            k_jump<<<nblocks(m.n_vlab), TPB, 0, st>>>(P<int>(m.vlab), m.n_vlab, P<unsigned>(c->flags));
+            k_jump<<<nblocks(m.n_tlab), TPB, 0, st>>>(P<int>(m.tlab), m.n_tlab, P<unsigned>(c->flags));
             CHECK_LAUNCH(c);
             HIPCHK(c, hipMemcpyAsync(c->hscratch, c->flags.p, sizeof(unsigned), hipMemcpyDeviceToHost, st));
             HIPCHK(c, hipStreamSynchronize(st));
             if (*reinterpret_cast<unsigned*>(c->hscratch) == 0) break;
         }
     }
-    c->have_msc = true;
+    m.valid = true;
     return DMT_OK;
 }
 
@@ -291,273 +321,365 @@ dmt_status read_counters(dmt_context* c, hipStream_t st) {
     return DMT_OK;
 }
 
-// Frontier loop: the iterations run on the device in batches; the host reads the control block
-// once per batch and grows the log buffer ahead of the next batch.
+// ---- one correction job --------------------------------------------------------------------
+
+struct Job {
+    int D = 2;
+    Dims dm{};
+    const float* f = nullptr;
+    const float* gh = nullptr;
+    float xi = 0.0f;
+    dmt_options o{};
+    float* g_out = nullptr;
+    uint8_t* q_out = nullptr;
+    JobWs* w = nullptr;
+    FrontierBufs B{};
+    dmt_stats stats{};
+    dmt_status status = DMT_OK;
+};
+
+// a0 (floors, validation flag into *flag) and a1 (gradient of f): launches only.
 template <int D>
-dmt_status frontier_loop(dmt_context* c, const Dims& dm, const float* f, const float* gh, const float* lo, float* g,
-                         uint8_t* state, const uint8_t* fpl, uint8_t* gpl, float delta, const dmt_options* o,
-                         int64_t& it, int64_t& c_it, int64_t& s_it, int64_t& residual, int& converged,
-                         int& stalled, hipStream_t st) {
-    const int n = dm.n;
-    ENSURE(c, c->ctl, sizeof(Ctl));
-    ENSURE(c, c->vmask, sizeof(uint32_t) * n);
-    ENSURE(c, c->inlist, n);
-    ENSURE(c, c->vl0, sizeof(int) * n);
-    ENSURE(c, c->vl1, sizeof(int) * n);
-    ENSURE(c, c->dvl0, sizeof(int) * n);
-    ENSURE(c, c->dvl1, sizeof(int) * n);
-    ENSURE(c, c->dal0, sizeof(int) * n);
-    ENSURE(c, c->dal1, sizeof(int) * n);
-    ENSURE(c, c->vstamp, sizeof(unsigned) * n);
-    ENSURE(c, c->astamp, sizeof(unsigned) * n);
-    ENSURE(c, c->rstamp, sizeof(unsigned) * n);
-    ENSURE(c, c->reql, sizeof(int) * n);
-    HIPCHK(c, hipMemsetAsync(c->inlist.p, 0, n, st));
-    HIPCHK(c, hipMemsetAsync(c->vstamp.p, 0, sizeof(unsigned) * n, st));
-    HIPCHK(c, hipMemsetAsync(c->astamp.p, 0, sizeof(unsigned) * n, st));
-    HIPCHK(c, hipMemsetAsync(c->rstamp.p, 0, sizeof(unsigned) * n, st));
-    k_fr_init<<<1, 1, 0, st>>>(P<Ctl>(c->ctl));
+dmt_status job_setup(dmt_context* c, Job& J, unsigned* flag, hipStream_t st) {
+    JobWs& w = *J.w;
+    const int n = J.dm.n;
+    ENSURE(c, w.lo, sizeof(float) * n);
+    ENSURE(c, w.g0, sizeof(float) * n);
+    ENSURE(c, w.state, n);
+    ENSURE(c, w.fpl, (size_t)Geom<D>::NB * n);
+    ENSURE(c, w.gpl, (size_t)Geom<D>::NB * n);
+    ENSURE(c, c->req, n);
+    {
+        ProfScope ps(c, DMT_PROF_SETUP, st, n);
+        k_setup<<<nblocks(n), TPB, 0, st>>>(J.f, J.gh, J.xi, n, P<float>(w.lo), P<float>(w.g0), P<uint8_t>(w.state),
+                                             P<uint8_t>(c->req), flag);
+        CHECK_LAUNCH(c);
+    }
+    return launch_grad(c, D, J.f, P<uint8_t>(w.fpl), J.dm, st);
+}
+
+// a2 (f-branches), frontier buffers and control block of a job whose setup passed; fills J.B.
+template <int D>
+dmt_status job_frontier(dmt_context* c, Job& J, hipStream_t st) {
+    JobWs& w = *J.w;
+    const int n = J.dm.n;
+    w.msc.valid = false;
+    if (J.o.tier >= 3) {
+        ProfScope ps(c, DMT_PROF_MSC, st, n);
+        TRY(build_msc<D>(c, w.msc, P<uint8_t>(w.fpl), J.dm, false, st));
+    }
+    ENSURE(c, w.ctl, sizeof(Ctl));
+    ENSURE(c, w.g1, sizeof(float) * n);
+    ENSURE(c, w.vmask, sizeof(uint32_t) * n);
+    ENSURE(c, w.vl0, sizeof(int) * n);
+    ENSURE(c, w.vl1, sizeof(int) * n);
+    ENSURE(c, w.dvl0, sizeof(int) * n);
+    ENSURE(c, w.dvl1, sizeof(int) * n);
+    ENSURE(c, w.dal0, sizeof(int) * n);
+    ENSURE(c, w.dal1, sizeof(int) * n);
+    ENSURE(c, w.vstamp, sizeof(unsigned) * n);
+    ENSURE(c, w.astamp, sizeof(unsigned) * n);
+    ENSURE(c, w.astamp1, sizeof(unsigned) * n);
+    ENSURE(c, w.rstamp, sizeof(unsigned) * n);
+    HIPCHK(c, hipMemcpyAsync(w.g1.p, w.g0.p, sizeof(float) * n, hipMemcpyDeviceToDevice, st));
+    HIPCHK(c, hipMemsetAsync(w.vstamp.p, 0, sizeof(unsigned) * n, st));
+    HIPCHK(c, hipMemsetAsync(w.astamp.p, 0, sizeof(unsigned) * n, st));
+    HIPCHK(c, hipMemsetAsync(w.astamp1.p, 0, sizeof(unsigned) * n, st));
+    HIPCHK(c, hipMemsetAsync(w.rstamp.p, 0, sizeof(unsigned) * n, st));
+    k_fr_init<<<1, 1, 0, st>>>(P<Ctl>(w.ctl));
     CHECK_LAUNCH(c);
 
-    FrontierBufs B{};
-    B.ctl = P<Ctl>(c->ctl);
-    B.f = f; B.gh = gh; B.lo = lo; B.g = g; B.state = state; B.fpl = fpl; B.gpl = gpl;
-    B.vmask = P<uint32_t>(c->vmask);
-    B.inlist = P<uint8_t>(c->inlist);
-    B.vl[0] = P<int>(c->vl0); B.vl[1] = P<int>(c->vl1);
-    B.dvl[0] = P<int>(c->dvl0); B.dvl[1] = P<int>(c->dvl1);
-    B.dal[0] = P<int>(c->dal0); B.dal[1] = P<int>(c->dal1);
-    B.vstamp = P<unsigned>(c->vstamp); B.astamp = P<unsigned>(c->astamp); B.rstamp = P<unsigned>(c->rstamp);
-    B.reql = P<int>(c->reql);
-    if (o->tier >= 3 && c->have_msc) {
-        B.dcell = P<int>(c->dcell); B.dcbr = P<int>(c->dcbr); B.dterm = P<int>(c->dterm);
-        B.acell = P<int>(c->acell); B.acbr = P<int>(c->acbr); B.aterm = P<int>(c->aterm);
-        B.doff = P<int64_t>(c->doff); B.aoff = P<int64_t>(c->aoff);
-        B.dfirst = P<int>(c->dfirst); B.afirst = P<int>(c->afirst);
-        B.n_dcell = c->n_desc_cells; B.n_acell = c->n_asc_cells;
-        B.n_desc = (int)c->n_desc; B.n_asc = (int)c->n_asc;
+    FrontierBufs& B = J.B;
+    B = FrontierBufs{};
+    B.ctl = P<Ctl>(w.ctl);
+    B.f = J.f;
+    B.gh = J.gh;
+    B.lo = P<float>(w.lo);
+    B.gb[0] = P<float>(w.g0);
+    B.gb[1] = P<float>(w.g1);
+    B.state = P<uint8_t>(w.state);
+    B.fpl = P<uint8_t>(w.fpl);
+    B.gpl = P<uint8_t>(w.gpl);
+    B.vmask = P<uint32_t>(w.vmask);
+    B.vl[0] = P<int>(w.vl0);
+    B.vl[1] = P<int>(w.vl1);
+    B.dvl[0] = P<int>(w.dvl0);
+    B.dvl[1] = P<int>(w.dvl1);
+    B.dal[0] = P<int>(w.dal0);
+    B.dal[1] = P<int>(w.dal1);
+    B.vstamp = P<unsigned>(w.vstamp);
+    B.astamp[0] = P<unsigned>(w.astamp);
+    B.astamp[1] = P<unsigned>(w.astamp1);
+    B.rstamp = P<unsigned>(w.rstamp);
+    B.log = nullptr;
+    if (w.msc.valid) {
+        MscBufs& m = w.msc;
+        B.dcell = P<int>(m.dcell); B.dcbr = P<int>(m.dcbr); B.dterm = P<int>(m.dterm);
+        B.acell = P<int>(m.acell); B.acbr = P<int>(m.acbr); B.aterm = P<int>(m.aterm);
+        B.doff = P<int64_t>(m.doff); B.aoff = P<int64_t>(m.aoff);
+        B.dfirst = P<int>(m.dfirst); B.afirst = P<int>(m.afirst);
+        B.n_dcell = m.n_desc_cells; B.n_acell = m.n_asc_cells;
+        B.n_desc = (int)m.n_desc; B.n_asc = (int)m.n_asc;
     }
-    B.delta = delta;
-    B.q_max = o->q_max;
-    B.tier = o->tier;
-    B.max_iters = o->max_iters < 0 ? INT64_MAX : o->max_iters;
-
-    // Persistent form: one cooperative launch runs the loop with grid barriers; it pauses when
-    // the log buffer is full, and the host grows the buffer and launches it again.
-    size_t log_cap = c->dlog.cap / (sizeof(long long) * DMT_LOG_WORDS);
-    auto grow_log = [&](size_t need, int64_t keep) -> dmt_status {
-        if (need <= log_cap) return DMT_OK;
-        const size_t ncap = need * 2;
-        DevBuf nb;
-        if (hipMalloc(&nb.p, ncap * sizeof(long long) * DMT_LOG_WORDS) != hipSuccess) {
-            (void)hipGetLastError();
-            return fail(c, DMT_E_NOMEM, "log allocation failed");
-        }
-        nb.cap = ncap * sizeof(long long) * DMT_LOG_WORDS;
-        if (c->dlog.p && keep > 0)
-            HIPCHK(c, hipMemcpyAsync(nb.p, c->dlog.p, (size_t)keep * sizeof(long long) * DMT_LOG_WORDS,
-                                     hipMemcpyDeviceToDevice, st));
-        HIPCHK(c, hipStreamSynchronize(st));
-        if (c->dlog.p) (void)hipFree(c->dlog.p);
-        c->dlog = nb;
-        log_cap = ncap;
-        return DMT_OK;
-    };
-    bool persistent = !(o->flags & DMT_F_PHASES);
-    int coop_blocks = 0;
-    if (persistent) {
-        int ncu = 0, occ = 0, coop = 0;
-        HIPCHK(c, hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, c->device));
-        HIPCHK(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device));
-        HIPCHK(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(k_fr_loop<D>),
-                                                               TPB, 0));
-        // The persistent grid only has to cover the frontier (iteration 0 runs as full-grid launches),
-        // and a grid barrier costs more the more blocks arrive at it, so the grid is small.
-        int want = 32;
-        if (const char* e = getenv("DMT_COOP_BLOCKS")) want = atoi(e) > 0 ? atoi(e) : want;
-        coop_blocks = want < ncu * occ ? want : ncu * occ;
-        persistent = coop && coop_blocks > 0;
-    }
-    int64_t host_it = 0;
-    if (persistent) {
-        const unsigned long long timeout = 500000000ull;   // 5 s of the 100 MHz wall clock
-        {
-            // iteration 0: dense gradient of g and violation masks of every anchor
-            const unsigned gfull = nblocks(n) < 2048u ? nblocks(n) : 2048u;
-            ProfScope ps(c, DMT_PROF_GRADIENT, st, n);
-            k_fr_grad<D><<<gfull, TPB, 0, st>>>(B, dm);
-            k_fr_vmask<D><<<gfull, TPB, 0, st>>>(B, dm);
-            CHECK_LAUNCH(c);
-        }
-        for (;;) {
-            dmt_status gs = grow_log((size_t)host_it + 4096, host_it);
-            if (gs != DMT_OK) return gs;
-            B.log = P<long long>(c->dlog);
-            int cap = (int)(log_cap < (size_t)INT32_MAX ? log_cap : (size_t)INT32_MAX);
-            void* args[] = {&B, (void*)&dm, &cap, (void*)&timeout};
-            {
-                ProfScope ps(c, DMT_PROF_LOOP, st, 0);
-                HIPCHK(c, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_fr_loop<D>), dim3(coop_blocks),
-                                                     dim3(TPB), args, 0, st));
-            }
-            HIPCHK(c, hipMemcpyAsync(c->hctl, c->ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, st));
-            HIPCHK(c, hipStreamSynchronize(st));
-            if (c->hctl->err) return fail(c, DMT_E_HIP, "grid barrier timed out in the persistent loop");
-            host_it = c->hctl->it;
-            if (c->hctl->done != 4) break;
-            const int zero = 0;
-            HIPCHK(c, hipMemcpyAsync(&P<Ctl>(c->ctl)->done, &zero, sizeof(int), hipMemcpyHostToDevice, st));
-        }
-    } else {
-        // Launch-per-phase form: batches of iterations without host synchronisation.
-        const unsigned gfull = nblocks(n) < 2048u ? nblocks(n) : 2048u;
-        int batch = 4;
-        for (;;) {
-            dmt_status gs = grow_log((size_t)host_it + (size_t)batch + 1, host_it);
-            if (gs != DMT_OK) return gs;
-            B.log = P<long long>(c->dlog);
-            for (int b = 0; b < batch; b++) {
-                ProfScope ps(c, DMT_PROF_LOOP, st, 0);
-                k_fr_grad<D><<<gfull, TPB, 0, st>>>(B, dm);
-                k_fr_vmask<D><<<gfull, TPB, 0, st>>>(B, dm);
-                k_fr_requests<D><<<gfull, TPB, 0, st>>>(B, dm);
-                if (o->tier >= 3) {
-                    k_fr_scheck<D><<<gfull, TPB, 0, st>>>(B, dm);
-                    k_fr_stargets<D><<<gfull, TPB, 0, st>>>(B, dm);
-                }
-                k_fr_apply<D><<<gfull, TPB, 0, st>>>(B, dm);
-                k_fr_finish<<<1, 1, 0, st>>>(B);
-                CHECK_LAUNCH(c);
-            }
-            HIPCHK(c, hipMemcpyAsync(c->hctl, c->ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, st));
-            HIPCHK(c, hipStreamSynchronize(st));
-            host_it = c->hctl->it;
-            if (c->hctl->done) break;
-            if (batch < 256) batch *= 2;
-        }
-    }
-    it = c->hctl->it;
-    c_it = c->hctl->c_it;
-    s_it = c->hctl->s_it;
-    residual = c->hctl->residual;
-    converged = c->hctl->done == 1;
-    stalled = c->hctl->done == 3;
-    c->log.assign((size_t)it * DMT_LOG_WORDS, 0);
-    if (it > 0)
-        HIPCHK(c, hipMemcpy(c->log.data(), c->dlog.p, sizeof(long long) * DMT_LOG_WORDS * (size_t)it,
-                            hipMemcpyDeviceToHost));
+    B.delta = ldexpf(J.xi, -J.o.q_max);
+    B.q_max = J.o.q_max;
+    B.tier = J.o.tier;
+    B.max_iters = J.o.max_iters < 0 ? INT64_MAX : J.o.max_iters;
     return DMT_OK;
 }
 
+// Iteration 0's dense gradient of g and violation pass, as full-grid launches.
 template <int D>
-dmt_status correct_impl(dmt_context* c, const Dims& dm, const float* f, const float* gh, float xi,
-                        const dmt_options* o, float* g_out, uint8_t* q_out, dmt_stats* stats, hipStream_t st) {
-    const int n = dm.n;
-    const unsigned nb = nblocks(n);
-    const float delta = ldexpf(xi, -o->q_max);
-    const int tier = o->tier;
-    ENSURE(c, c->lo, sizeof(float) * n);
-    ENSURE(c, c->g, sizeof(float) * n);
-    ENSURE(c, c->state, n);
-    ENSURE(c, c->req, n);
-    ENSURE(c, c->fpl, (size_t)Geom<D>::NB * n);
-    ENSURE(c, c->gpl, (size_t)Geom<D>::NB * n);
-    ENSURE(c, c->cnt, sizeof(unsigned long long) * CNT_WORDS);
-    ENSURE(c, c->flags, 16);
-    ENSURE(c, c->blk, sizeof(int) * (size_t)(D + 1) * nb);
-    ENSURE(c, c->blkoff, sizeof(int64_t) * (size_t)(D + 1) * (nb + 1));
-    unsigned long long* cnt = P<unsigned long long>(c->cnt);
-    float* lo = P<float>(c->lo);
-    float* g = P<float>(c->g);
-    uint8_t* state = P<uint8_t>(c->state);
-    uint8_t* req = P<uint8_t>(c->req);
-    uint8_t* fpl = P<uint8_t>(c->fpl);
-    uint8_t* gpl = P<uint8_t>(c->gpl);
+dmt_status job_iteration0(dmt_context* c, Job& J, hipStream_t st) {
+    const int n = J.dm.n;
+    const unsigned gfull = nblocks(n) < 2048u ? nblocks(n) : 2048u;
+    ProfScope ps(c, DMT_PROF_GRADIENT, st, n);
+    k_fr_grad<D><<<gfull, TPB, 0, st>>>(J.B, J.dm);
+    k_fr_vr<D><<<gfull, TPB, 0, st>>>(J.B, J.dm);
+    CHECK_LAUNCH(c);
+    return DMT_OK;
+}
 
-    // a0: floors, validation, state
-    HIPCHK(c, hipMemsetAsync(c->flags.p, 0, sizeof(unsigned), st));
-    {
-        ProfScope ps(c, DMT_PROF_SETUP, st, n);
-        k_setup<<<nb, TPB, 0, st>>>(f, gh, xi, n, lo, g, state, req, P<unsigned>(c->flags));
-        CHECK_LAUNCH(c);
+// Grows the single-job log buffer to hold need records, keeping the first keep.
+dmt_status grow_log(dmt_context* c, size_t need, int64_t keep, hipStream_t st) {
+    const size_t rec = sizeof(long long) * DMT_LOG_WORDS;
+    if (c->dlog.cap >= need * rec) return DMT_OK;
+    DevBuf nb;
+    if (hipMalloc(&nb.p, need * 2 * rec) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, DMT_E_NOMEM, "log allocation failed");
     }
-    HIPCHK(c, hipMemcpyAsync(c->hscratch, c->flags.p, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+    nb.cap = need * 2 * rec;
+    if (c->dlog.p && keep > 0)
+        HIPCHK(c, hipMemcpyAsync(nb.p, c->dlog.p, (size_t)keep * rec, hipMemcpyDeviceToDevice, st));
     HIPCHK(c, hipStreamSynchronize(st));
-    const unsigned fl = *reinterpret_cast<unsigned*>(c->hscratch);
-    if (fl & 1u) return fail(c, DMT_E_NONFINITE, "non-finite value in f or g_hat");
-    if (fl & 2u) return fail(c, DMT_E_BOUND, "|g_hat - f| > xi somewhere");
+    if (c->dlog.p) (void)hipFree(c->dlog.p);
+    c->dlog = nb;
+    return DMT_OK;
+}
 
-    // a1, a2: gradient of f and its separatrix branches (fixed for the whole run)
-    dmt_status s = launch_grad(c, D, f, fpl, dm, st);
-    if (s != DMT_OK) return s;
-    c->have_msc = false;
-    if (tier >= 3) {
-        ProfScope ps(c, DMT_PROF_MSC, st, n);
-        s = build_msc<D>(c, fpl, dm, false, st);
-        if (s != DMT_OK) return s;
-    }
+// The persistent loop over the jobs (one cooperative launch).  A single job may keep a log; the
+// kernel pauses when it is full and is launched again after the log has grown.
+dmt_status run_persistent(dmt_context* c, std::vector<Job*>& jobs, bool with_log, hipStream_t st) {
+    const int nj = (int)jobs.size();
+    int ncu = 0, occ = 0, coop = 0;
+    HIPCHK(c, hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, c->device));
+    HIPCHK(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device));
+    HIPCHK(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(k_fr_loop_batch), TPB, 0));
+    if (!coop || occ < 1) return fail(c, DMT_E_HIP, "cooperative launch unavailable");
+    // The persistent grid only covers frontiers (iteration 0 runs as full-grid launches), and a
+    // grid barrier costs more the more blocks arrive at it, so the grid is small.
+    int want = 32;
+    if (const char* e = getenv("DMT_COOP_BLOCKS")) want = atoi(e) > 0 ? atoi(e) : want;
+    const int blocks = want < ncu * occ ? want : ncu * occ;
 
-    c->log.clear();
-    int64_t it = 0, c_it = 0, s_it = 0, residual = 0;
-    int converged = 0, stalled = 0;
-    const int64_t max_iters = o->max_iters < 0 ? INT64_MAX : o->max_iters;
-    if (!(o->flags & DMT_F_DENSE)) {
-        s = frontier_loop<D>(c, dm, f, gh, lo, g, state, fpl, gpl, delta, o, it, c_it, s_it, residual, converged,
-                             stalled, st);
-        if (s != DMT_OK) return s;
+    ENSURE(c, c->jobs_dev, sizeof(FrontierBufs) * nj);
+    ENSURE(c, c->dims_dev, sizeof(Dims) * nj);
+    ENSURE(c, c->run_dev, sizeof(JobRun) * nj);
+    ENSURE(c, c->bctl, sizeof(BatchCtl));
+    std::vector<FrontierBufs> hb(nj);
+    std::vector<Dims> hd(nj);
+    std::vector<JobRun> hr(nj);
+    if (with_log) TRY(grow_log(c, 4096, 0, st));
+    const int cap0 = with_log ? (int)(c->dlog.cap / (sizeof(long long) * DMT_LOG_WORDS)) : 0;
+    for (int j = 0; j < nj; j++) {
+        hb[j] = jobs[j]->B;
+        if (with_log) hb[j].log = P<long long>(c->dlog);
+        hd[j] = jobs[j]->dm;
+        hr[j] = JobRun{{0, 0}, {0, 0}, cap0, jobs[j]->D};
     }
-    for (; o->flags & DMT_F_DENSE;) {
-        s = launch_grad(c, D, g, gpl, dm, st);
-        if (s != DMT_OK) return s;
-        HIPCHK(c, hipMemsetAsync(cnt, 0, sizeof(unsigned long long) * CNT_WORDS, st));
+    *c->hbctl = BatchCtl{};
+    HIPCHK(c, hipMemcpyAsync(c->jobs_dev.p, hb.data(), sizeof(FrontierBufs) * nj, hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipMemcpyAsync(c->dims_dev.p, hd.data(), sizeof(Dims) * nj, hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipMemcpyAsync(c->run_dev.p, hr.data(), sizeof(JobRun) * nj, hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipMemcpyAsync(c->bctl.p, c->hbctl, sizeof(BatchCtl), hipMemcpyHostToDevice, st));
+    // Every iteration that does not end a job edits at least one vertex, and a vertex takes at
+    // most q_max + 1 edits (Section 4.6), so no job runs more than n (q_max + 1) + 1 iterations.
+    int64_t bound = 0;
+    for (Job* J : jobs) {
+        const int64_t b = (int64_t)J->dm.n * (J->o.q_max + 1) + 1;
+        bound = b > bound ? b : bound;
+    }
+    const int max_passes = 1 << 16;
+    for (;;) {
+        const FrontierBufs* jp = P<FrontierBufs>(c->jobs_dev);
+        const Dims* dp = P<Dims>(c->dims_dev);
+        JobRun* rp = P<JobRun>(c->run_dev);
+        BatchCtl* bp = P<BatchCtl>(c->bctl);
+        int njobs = nj;
+        unsigned long long timeout = 500000000ull;   // 5 s of the 100 MHz wall clock
+        int mp = max_passes;
+        void* args[] = {&jp, &dp, &rp, &njobs, &bp, &timeout, &mp};
         {
-            ProfScope ps(c, DMT_PROF_CLASSIFY, st, n);
-            k_classify<D><<<nb, TPB, 0, st>>>(fpl, gpl, f, g, req, dm, tier, cnt);
+            ProfScope ps(c, DMT_PROF_LOOP, st, 0);
+            HIPCHK(c, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_fr_loop_batch), dim3(blocks),
+                                                 dim3(TPB), args, 0, st));
+        }
+        HIPCHK(c, hipMemcpyAsync(c->hbctl, c->bctl.p, sizeof(BatchCtl), hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipMemcpyAsync(hr.data(), c->run_dev.p, sizeof(JobRun) * nj, hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        if (c->hbctl->err) return fail(c, DMT_E_HIP, "grid barrier timed out in the persistent loop");
+        const int q = c->hbctl->parity & 1;
+        bool paused = false, log_full = false;
+        int64_t max_it = 0;
+        for (int j = 0; j < nj; j++) {
+            if (hr[j].donep[q]) continue;
+            paused = true;
+            max_it = hr[j].itp[q] > max_it ? hr[j].itp[q] : max_it;
+            if (with_log && hr[j].itp[q] >= hr[j].log_cap) log_full = true;
+        }
+        if (!paused) break;
+        // parity counts the passes of every launch so far
+        if (max_it > bound || (int64_t)c->hbctl->parity > bound + 1)
+            return fail(c, DMT_E_HIP, "persistent loop exceeded the iteration bound");
+        if (!log_full) continue;   // pass budget of the launch used up: launch again
+        // the log is full: grow it, point the job at it and resume
+        const int64_t host_it = hr[0].itp[q];
+        TRY(grow_log(c, (size_t)host_it * 2 + 4096, host_it, st));
+        hb[0].log = P<long long>(c->dlog);
+        const int cap = (int)(c->dlog.cap / (sizeof(long long) * DMT_LOG_WORDS));
+        HIPCHK(c, hipMemcpyAsync(c->jobs_dev.p, hb.data(), sizeof(FrontierBufs), hipMemcpyHostToDevice, st));
+        HIPCHK(c, hipMemcpyAsync(&P<JobRun>(c->run_dev)->log_cap, &cap, sizeof(int), hipMemcpyHostToDevice, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+    }
+    return DMT_OK;
+}
+
+// The frontier loop as one launch per phase (single job), host synchronisation once per batch.
+template <int D>
+dmt_status run_phases(dmt_context* c, Job& J, hipStream_t st) {
+    const int n = J.dm.n;
+    const unsigned gfull = nblocks(n) < 2048u ? nblocks(n) : 2048u;
+    int batch = 4;
+    int64_t host_it = 0;
+    Ctl h{};
+    for (;;) {
+        TRY(grow_log(c, (size_t)host_it + (size_t)batch + 1, host_it, st));
+        J.B.log = P<long long>(c->dlog);
+        for (int b = 0; b < batch; b++) {
+            ProfScope ps(c, DMT_PROF_LOOP, st, 0);
+            k_fr_grad<D><<<gfull, TPB, 0, st>>>(J.B, J.dm);
+            k_fr_vr<D><<<gfull, TPB, 0, st>>>(J.B, J.dm);
+            if (J.o.tier >= 3) k_fr_sapply<D><<<gfull, TPB, 0, st>>>(J.B, J.dm);
+            k_fr_finish<<<1, 1, 0, st>>>(J.B);
             CHECK_LAUNCH(c);
         }
-        s = read_counters(c, st);
-        if (s != DMT_OK) return s;
+        HIPCHK(c, hipMemcpyAsync(&h, J.B.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        host_it = h.it;
+        if (h.done) break;
+        if (host_it > (int64_t)n * (J.o.q_max + 1) + 1)   // the bound of run_persistent
+            return fail(c, DMT_E_HIP, "phase loop exceeded the iteration bound");
+        if (batch < 256) batch *= 2;
+    }
+    return DMT_OK;
+}
+
+// a8: g_out, q_out and statistics of a finished job; the field of the last iteration is in
+// gb[it & 1].
+dmt_status job_outputs(dmt_context* c, Job& J, const Ctl& ctl, bool lossless_list, hipStream_t st) {
+    const int n = J.dm.n;
+    const unsigned nb = nblocks(n);
+    JobWs& w = *J.w;
+    float* gfin = J.B.gb[ctl.it & 1];
+    ENSURE(c, c->cnt, sizeof(unsigned long long) * CNT_WORDS);
+    ENSURE(c, c->blk, sizeof(int) * (size_t)nb);
+    ENSURE(c, c->blkoff, sizeof(int64_t) * (size_t)(nb + 1));
+    unsigned long long* cnt = P<unsigned long long>(c->cnt);
+    HIPCHK(c, hipMemcpyAsync(J.g_out, gfin, sizeof(float) * n, hipMemcpyDeviceToDevice, st));
+    HIPCHK(c, hipMemsetAsync(cnt, 0, sizeof(unsigned long long) * CNT_WORDS, st));
+    k_qout<<<nb, TPB, 0, st>>>(P<uint8_t>(w.state), gfin, J.gh, J.q_out, n, P<int>(c->blk), cnt);
+    CHECK_LAUNCH(c);
+    if (lossless_list) {
+        TRY(scan(c, P<int>(c->blk), nb, P<int64_t>(c->blkoff), &c->n_lossless, st));
+        ENSURE(c, c->ll_idx, sizeof(int64_t) * (size_t)c->n_lossless);
+        ENSURE(c, c->ll_val, sizeof(float) * (size_t)c->n_lossless);
+        k_lossless_write<<<nb, TPB, 0, st>>>(J.q_out, gfin, n, P<int64_t>(c->blkoff), P<int64_t>(c->ll_idx),
+                                             P<float>(c->ll_val));
+        CHECK_LAUNCH(c);
+    }
+    TRY(read_counters(c, st));
+    dmt_stats& S = J.stats;
+    S.iterations = ctl.it;
+    S.c_iterations = ctl.c_it;
+    S.s_iterations = ctl.s_it;
+    S.n_edited = (int64_t)c->hcnt[CNT_EDITED];
+    S.n_quantized = (int64_t)c->hcnt[CNT_QUANT];
+    S.n_lossless = (int64_t)c->hcnt[CNT_LOSSLESS];
+    S.residual_violations = ctl.done == 1 ? 0 : ctl.residual;
+    S.converged = ctl.done == 1;
+    S.stalled = ctl.done == 3;
+    J.status = ctl.done == 1 ? DMT_OK : DMT_W_NOT_CONVERGED;
+    return DMT_OK;
+}
+
+// ---- dense reference loop (DMT_F_DENSE): whole gradient and every anchor each iteration ------
+
+template <int D>
+dmt_status dense_loop(dmt_context* c, Job& J, Ctl& out, hipStream_t st) {
+    const Dims& dm = J.dm;
+    const int n = dm.n;
+    const unsigned nb = nblocks(n);
+    JobWs& w = *J.w;
+    const float delta = ldexpf(J.xi, -J.o.q_max);
+    const int tier = J.o.tier;
+    ENSURE(c, c->cnt, sizeof(unsigned long long) * CNT_WORDS);
+    unsigned long long* cnt = P<unsigned long long>(c->cnt);
+    float* lo = P<float>(w.lo);
+    float* g = P<float>(w.g0);
+    uint8_t* state = P<uint8_t>(w.state);
+    uint8_t* req = P<uint8_t>(c->req);
+    uint8_t* fpl = P<uint8_t>(w.fpl);
+    uint8_t* gpl = P<uint8_t>(w.gpl);
+    MscBufs& m = w.msc;
+    m.valid = false;
+    if (tier >= 3) TRY(build_msc<D>(c, m, fpl, dm, false, st));
+    c->log.clear();
+    int64_t it = 0, c_it = 0, s_it = 0, residual = 0;
+    int done = 0;
+    const int64_t max_iters = J.o.max_iters < 0 ? INT64_MAX : J.o.max_iters;
+    for (;;) {
+        TRY(launch_grad(c, D, g, gpl, dm, st));
+        HIPCHK(c, hipMemsetAsync(cnt, 0, sizeof(unsigned long long) * CNT_WORDS, st));
+        k_classify<D><<<nb, TPB, 0, st>>>(fpl, gpl, J.f, g, req, dm, tier, cnt);
+        CHECK_LAUNCH(c);
+        TRY(read_counters(c, st));
         int64_t viol = 0;
         for (int k = CNT_FP0; k < CNT_FP0 + 8; k++) viol += (int64_t)c->hcnt[k];
         int kind = 1;
         if (viol == 0 && tier >= 3) {
             kind = 2;
-            ProfScope ps(c, DMT_PROF_SSTEP, st, c->n_desc_cells + c->n_asc_cells);
-            if (c->n_desc_cells) {
-                k_scheck_desc<<<nblocks(c->n_desc_cells), TPB, 0, st>>>(fpl, gpl, P<int>(c->dcell), P<int>(c->dcbr),
-                                                                        c->n_desc_cells, P<int>(c->dfirst));
-                k_starget<D><<<nblocks(c->n_desc), TPB, 0, st>>>(fpl, gpl, dm, 0, P<int>(c->dcell), P<int64_t>(c->doff),
-                                                                 P<int>(c->dterm), (int)c->n_desc, P<int>(c->dfirst),
-                                                                 tier, req, cnt);
+            if (m.n_desc_cells) {
+                k_scheck_desc<<<nblocks(m.n_desc_cells), TPB, 0, st>>>(fpl, gpl, P<int>(m.dcell), P<int>(m.dcbr),
+                                                                       m.n_desc_cells, P<int>(m.dfirst));
+                k_starget<D><<<nblocks(m.n_desc), TPB, 0, st>>>(fpl, gpl, dm, 0, P<int>(m.dcell), P<int64_t>(m.doff),
+                                                                P<int>(m.dterm), (int)m.n_desc, P<int>(m.dfirst), tier,
+                                                                req, cnt);
                 CHECK_LAUNCH(c);
             }
-            if (c->n_asc_cells) {
-                k_scheck_asc<D><<<nblocks(c->n_asc_cells), TPB, 0, st>>>(fpl, gpl, dm, P<int>(c->acell), P<int>(c->acbr),
-                                                                         c->n_asc_cells, P<int>(c->afirst));
-                k_starget<D><<<nblocks(c->n_asc), TPB, 0, st>>>(fpl, gpl, dm, 1, P<int>(c->acell), P<int64_t>(c->aoff),
-                                                                P<int>(c->aterm), (int)c->n_asc, P<int>(c->afirst),
-                                                                tier, req, cnt);
+            if (m.n_asc_cells) {
+                k_scheck_asc<D><<<nblocks(m.n_asc_cells), TPB, 0, st>>>(fpl, gpl, dm, P<int>(m.acell), P<int>(m.acbr),
+                                                                        m.n_asc_cells, P<int>(m.afirst));
+                k_starget<D><<<nblocks(m.n_asc), TPB, 0, st>>>(fpl, gpl, dm, 1, P<int>(m.acell), P<int64_t>(m.aoff),
+                                                               P<int>(m.aterm), (int)m.n_asc, P<int>(m.afirst), tier,
+                                                               req, cnt);
                 CHECK_LAUNCH(c);
             }
-            s = read_counters(c, st);
-            if (s != DMT_OK) return s;
+            TRY(read_counters(c, st));
             viol = (int64_t)(c->hcnt[CNT_TM_DESC] + c->hcnt[CNT_TM_ASC]);
         }
-        if (viol == 0) { converged = 1; break; }
+        if (viol == 0) { done = 1; break; }
         if (it == max_iters) {
             residual = viol;
+            done = 2;
             k_clear_u8<<<nb, TPB, 0, st>>>(req, n);
             CHECK_LAUNCH(c);
             break;
         }
-        {
-            ProfScope ps(c, DMT_PROF_APPLY, st, n);
-            k_apply<<<nb, TPB, 0, st>>>(req, gh, lo, g, state, delta, o->q_max, n, cnt);
-            CHECK_LAUNCH(c);
-        }
-        s = read_counters(c, st);
-        if (s != DMT_OK) return s;
-        if (c->hcnt[CNT_CHANGED] == 0) { stalled = 1; residual = viol; break; }
+        k_apply<<<nb, TPB, 0, st>>>(req, J.gh, lo, g, state, delta, J.o.q_max, n, cnt);
+        CHECK_LAUNCH(c);
+        TRY(read_counters(c, st));
+        if (c->hcnt[CNT_CHANGED] == 0) { done = 3; residual = viol; break; }
         int64_t rec[DMT_LOG_WORDS] = {0};
         rec[0] = kind;
         for (int k = 1; k <= CNT_CHANGED; k++) rec[k] = (int64_t)c->hcnt[k];
@@ -565,32 +687,70 @@ dmt_status correct_impl(dmt_context* c, const Dims& dm, const float* f, const fl
         it++;
         if (kind == 1) c_it++; else s_it++;
     }
+    out = Ctl{};
+    out.it = (int)it;
+    out.done = done;
+    out.c_it = (int)c_it;
+    out.s_it = (int)s_it;
+    out.residual = residual;
+    J.B.gb[0] = g;   // the single buffer of this form, whatever the parity of it
+    J.B.gb[1] = g;
+    return DMT_OK;
+}
 
-    // a8: outputs
-    HIPCHK(c, hipMemcpyAsync(g_out, g, sizeof(float) * n, hipMemcpyDeviceToDevice, st));
-    HIPCHK(c, hipMemsetAsync(cnt, 0, sizeof(unsigned long long) * CNT_WORDS, st));
-    k_qout<<<nb, TPB, 0, st>>>(state, g, gh, q_out, n, P<int>(c->blk), cnt);
-    CHECK_LAUNCH(c);
-    s = scan(c, P<int>(c->blk), nb, P<int64_t>(c->blkoff), &c->n_lossless, st);
-    if (s != DMT_OK) return s;
-    ENSURE(c, c->ll_idx, sizeof(int64_t) * (size_t)c->n_lossless);
-    ENSURE(c, c->ll_val, sizeof(float) * (size_t)c->n_lossless);
-    k_lossless_write<<<nb, TPB, 0, st>>>(q_out, g, n, P<int64_t>(c->blkoff), P<int64_t>(c->ll_idx), P<float>(c->ll_val));
-    CHECK_LAUNCH(c);
-    s = read_counters(c, st);
-    if (s != DMT_OK) return s;
-    if (stats) {
-        stats->iterations = it;
-        stats->c_iterations = c_it;
-        stats->s_iterations = s_it;
-        stats->n_edited = (int64_t)c->hcnt[CNT_EDITED];
-        stats->n_quantized = (int64_t)c->hcnt[CNT_QUANT];
-        stats->n_lossless = (int64_t)c->hcnt[CNT_LOSSLESS];
-        stats->residual_violations = residual;
-        stats->converged = converged;
-        stats->stalled = stalled;
+// ---- driver shared by dmt_correct and dmt_correct_batch -------------------------------------
+
+// Runs validated jobs.  single: one job; keeps the log and the lossless list in the context
+// and honours the DENSE / PHASES flags.
+dmt_status run_jobs(dmt_context* c, std::vector<Job>& jobs, bool single, hipStream_t st) {
+    const int nj = (int)jobs.size();
+    if ((int)c->ws.size() < nj) c->ws.resize(nj);
+    ENSURE(c, c->flags, sizeof(unsigned) * (nj + 1));
+    HIPCHK(c, hipMemsetAsync(c->flags.p, 0, sizeof(unsigned) * (nj + 1), st));
+    // a0, a1 for every job, then one look at the validation flags
+    for (int j = 0; j < nj; j++) {
+        jobs[j].w = &c->ws[j];
+        TRY(jobs[j].D == 2 ? job_setup<2>(c, jobs[j], P<unsigned>(c->flags) + 1 + j, st)
+                           : job_setup<3>(c, jobs[j], P<unsigned>(c->flags) + 1 + j, st));
     }
-    return converged ? DMT_OK : DMT_W_NOT_CONVERGED;
+    std::vector<unsigned> fl(nj + 1);
+    HIPCHK(c, hipMemcpyAsync(fl.data(), c->flags.p, sizeof(unsigned) * (nj + 1), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    std::vector<Job*> live;
+    for (int j = 0; j < nj; j++) {
+        const unsigned f = fl[1 + j];
+        if (f & 1u) { jobs[j].status = DMT_E_NONFINITE; continue; }
+        if (f & 2u) { jobs[j].status = DMT_E_BOUND; continue; }
+        live.push_back(&jobs[j]);
+    }
+    if (live.empty()) return DMT_OK;
+    c->hctl.assign(live.size(), Ctl{});
+    if (single && (jobs[0].o.flags & DMT_F_DENSE)) {
+        Job& J = jobs[0];
+        TRY(J.D == 2 ? dense_loop<2>(c, J, c->hctl[0], st) : dense_loop<3>(c, J, c->hctl[0], st));
+        return job_outputs(c, J, c->hctl[0], true, st);
+    }
+    // a2 and frontier state for every live job, then the loop
+    for (Job* J : live) TRY(J->D == 2 ? job_frontier<2>(c, *J, st) : job_frontier<3>(c, *J, st));
+    if (single && (jobs[0].o.flags & DMT_F_PHASES)) {
+        Job& J = jobs[0];
+        TRY(J.D == 2 ? run_phases<2>(c, J, st) : run_phases<3>(c, J, st));
+    } else {
+        for (Job* J : live) TRY(J->D == 2 ? job_iteration0<2>(c, *J, st) : job_iteration0<3>(c, *J, st));
+        TRY(run_persistent(c, live, single, st));
+    }
+    for (size_t k = 0; k < live.size(); k++)
+        HIPCHK(c, hipMemcpyAsync(&c->hctl[k], live[k]->B.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    for (size_t k = 0; k < live.size(); k++) TRY(job_outputs(c, *live[k], c->hctl[k], single, st));
+    if (single) {
+        const int64_t nrec = c->hctl[0].it;
+        c->log.assign((size_t)nrec * DMT_LOG_WORDS, 0);
+        if (nrec > 0)
+            HIPCHK(c, hipMemcpy(c->log.data(), c->dlog.p, sizeof(long long) * DMT_LOG_WORDS * (size_t)nrec,
+                                hipMemcpyDeviceToHost));
+    }
+    return DMT_OK;
 }
 
 }  // namespace
@@ -612,11 +772,12 @@ dmt_status dmt_context_create(dmt_context** ctx, int hip_device) {
     dmt_context* c = new dmt_context();
     c->device = hip_device;
     if (hipHostMalloc((void**)&c->hcnt, sizeof(unsigned long long) * CNT_WORDS, 0) != hipSuccess ||
-        hipHostMalloc((void**)&c->hctl, sizeof(Ctl), 0) != hipSuccess ||
+        hipHostMalloc((void**)&c->hbctl, sizeof(BatchCtl), 0) != hipSuccess ||
         hipHostMalloc((void**)&c->hscratch, sizeof(int64_t) * 64, 0) != hipSuccess) {
         delete c;
         return DMT_E_NOMEM;
     }
+    *c->hbctl = BatchCtl{};
     *ctx = c;
     return DMT_OK;
 }
@@ -624,17 +785,16 @@ dmt_status dmt_context_create(dmt_context** ctx, int hip_device) {
 dmt_status dmt_context_destroy(dmt_context* c) {
     if (!c) return DMT_OK;
     (void)hipSetDevice(c->device);
-    DevBuf* bufs[] = {&c->lo, &c->g, &c->state, &c->req, &c->fpl, &c->gpl, &c->cnt, &c->flags, &c->part, &c->blk,
-                      &c->blkoff, &c->crit[0], &c->crit[1], &c->crit[2], &c->crit[3], &c->dsad, &c->doff, &c->dcell,
-                      &c->dcbr, &c->dterm, &c->dlen, &c->dfirst, &c->asad, &c->aoff, &c->acell, &c->acbr, &c->aterm,
-                      &c->alen, &c->afirst, &c->astart, &c->asadcnt, &c->asadoff, &c->vlab, &c->tlab, &c->ll_idx,
-                      &c->ll_val, &c->ctl, &c->vmask, &c->inlist, &c->vl0, &c->vl1, &c->dvl0, &c->dvl1, &c->dal0,
-                      &c->dal1, &c->vstamp, &c->astamp, &c->rstamp, &c->reql, &c->dlog};
+    std::vector<DevBuf*> bufs = {&c->gpl, &c->req, &c->cnt, &c->flags, &c->part, &c->blk, &c->blkoff, &c->ll_idx,
+                                 &c->ll_val, &c->dlog, &c->jobs_dev, &c->dims_dev, &c->run_dev, &c->bctl};
+    for (DevBuf* b : c->msc.all()) bufs.push_back(b);
+    for (JobWs& w : c->ws)
+        for (DevBuf* b : w.all()) bufs.push_back(b);
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     if (c->hcnt) (void)hipHostFree(c->hcnt);
-    if (c->hctl) (void)hipHostFree(c->hctl);
+    if (c->hbctl) (void)hipHostFree(c->hbctl);
     if (c->hscratch) (void)hipHostFree(c->hscratch);
     delete c;
     return DMT_OK;
@@ -657,8 +817,7 @@ dmt_status dmt_xi_from_relative(dmt_context* c, const dmt_grid* gr, const float*
     if (!c || !f || !xi_host) return fail(c, DMT_E_INVALID, "null argument");
     Dims dm;
     int D;
-    dmt_status s = check_grid(c, gr, dm, D);
-    if (s != DMT_OK) return s;
+    TRY(check_grid(c, gr, dm, D));
     if (!(rel > 0.0) || !std::isfinite(rel)) return fail(c, DMT_E_INVALID, "rel must be finite and > 0");
     HIPCHK(c, hipSetDevice(c->device));
     const int nbk = 512;
@@ -671,8 +830,7 @@ dmt_status dmt_xi_from_relative(dmt_context* c, const dmt_grid* gr, const float*
     HIPCHK(c, hipStreamSynchronize(st));
     const float* h = reinterpret_cast<const float*>(c->hscratch);
     const float mn = h[0], mx = h[1];
-    const bool nonfinite = h[2] != 0.0f;
-    if (nonfinite) return fail(c, DMT_E_NONFINITE, "non-finite value in f");
+    if (h[2] != 0.0f) return fail(c, DMT_E_NONFINITE, "non-finite value in f");
     *xi_host = (float)(rel * ((double)mx - (double)mn));
     return DMT_OK;
 }
@@ -692,12 +850,10 @@ dmt_status dmt_gradient_pairs(dmt_context* c, const dmt_grid* gr, const float* f
     if (!c || !field || !up || !down) return fail(c, DMT_E_INVALID, "null argument");
     Dims dm;
     int D;
-    dmt_status s = check_grid(c, gr, dm, D);
-    if (s != DMT_OK) return s;
+    TRY(check_grid(c, gr, dm, D));
     HIPCHK(c, hipSetDevice(c->device));
     ENSURE(c, c->gpl, (size_t)nplanes(D) * dm.n);
-    s = launch_grad(c, D, field, P<uint8_t>(c->gpl), dm, st);
-    if (s != DMT_OK) return s;
+    TRY(launch_grad(c, D, field, P<uint8_t>(c->gpl), dm, st));
     const int64_t o1 = dm.n, o2 = o1 + (int64_t)dm.n * ntypes(D, 1), o3 = o2 + (int64_t)dm.n * ntypes(D, 2);
     if (D == 2) k_export<2><<<nblocks(dm.n), TPB, 0, st>>>(P<uint8_t>(c->gpl), dm, o1, o2, o3, up, down);
     else k_export<3><<<nblocks(dm.n), TPB, 0, st>>>(P<uint8_t>(c->gpl), dm, o1, o2, o3, up, down);
@@ -711,58 +867,58 @@ dmt_status dmt_extract_msc(dmt_context* c, const dmt_grid* gr, const float* fiel
     if (!c || !field || !counts) return fail(c, DMT_E_INVALID, "null argument");
     Dims dm;
     int D;
-    dmt_status s = check_grid(c, gr, dm, D);
-    if (s != DMT_OK) return s;
+    TRY(check_grid(c, gr, dm, D));
     HIPCHK(c, hipSetDevice(c->device));
     ENSURE(c, c->gpl, (size_t)nplanes(D) * dm.n);
-    s = launch_grad(c, D, field, P<uint8_t>(c->gpl), dm, st);
-    if (s != DMT_OK) return s;
-    s = D == 2 ? build_msc<2>(c, P<uint8_t>(c->gpl), dm, true, st) : build_msc<3>(c, P<uint8_t>(c->gpl), dm, true, st);
-    if (s != DMT_OK) return s;
+    TRY(launch_grad(c, D, field, P<uint8_t>(c->gpl), dm, st));
+    MscBufs& m = c->msc;
+    TRY(D == 2 ? build_msc<2>(c, m, P<uint8_t>(c->gpl), dm, true, st)
+               : build_msc<3>(c, m, P<uint8_t>(c->gpl), dm, true, st));
     HIPCHK(c, hipStreamSynchronize(st));
     for (int k = 0; k < 32; k++) counts[k] = 0;
-    for (int d = 0; d < 4; d++) counts[DMT_MSC_CRIT0 + d] = c->ncrit[d];
-    counts[DMT_MSC_DESC_SADDLE] = c->n_desc;
-    counts[DMT_MSC_DESC_OFFSETS] = c->n_desc + 1;
-    counts[DMT_MSC_DESC_CELLS] = c->n_desc_cells;
-    counts[DMT_MSC_DESC_TERMINAL] = c->n_desc;
-    counts[DMT_MSC_ASC_SADDLE] = c->n_asc;
-    counts[DMT_MSC_ASC_OFFSETS] = c->n_asc + 1;
-    counts[DMT_MSC_ASC_CELLS] = c->n_asc_cells;
-    counts[DMT_MSC_ASC_TERMINAL] = c->n_asc;
-    counts[DMT_MSC_MIN_LABEL] = c->n_vlab;
-    counts[DMT_MSC_MAX_LABEL] = c->n_tlab;
+    for (int d = 0; d < 4; d++) counts[DMT_MSC_CRIT0 + d] = m.ncrit[d];
+    counts[DMT_MSC_DESC_SADDLE] = m.n_desc;
+    counts[DMT_MSC_DESC_OFFSETS] = m.n_desc + 1;
+    counts[DMT_MSC_DESC_CELLS] = m.n_desc_cells;
+    counts[DMT_MSC_DESC_TERMINAL] = m.n_desc;
+    counts[DMT_MSC_ASC_SADDLE] = m.n_asc;
+    counts[DMT_MSC_ASC_OFFSETS] = m.n_asc + 1;
+    counts[DMT_MSC_ASC_CELLS] = m.n_asc_cells;
+    counts[DMT_MSC_ASC_TERMINAL] = m.n_asc;
+    counts[DMT_MSC_MIN_LABEL] = m.n_vlab;
+    counts[DMT_MSC_MAX_LABEL] = m.n_tlab;
     return DMT_OK;
 }
 
 dmt_status dmt_msc_copy(dmt_context* c, int item, int64_t* dst, int64_t cap, hipStream_t st) {
     if (!c || !dst) return fail(c, DMT_E_INVALID, "null argument");
-    if (!c->have_msc) return fail(c, DMT_E_INVALID, "no MSC extracted");
+    MscBufs& m = c->msc;
+    if (!m.valid) return fail(c, DMT_E_INVALID, "no MSC extracted");
     HIPCHK(c, hipSetDevice(c->device));
     const int* src32 = nullptr;
     const int64_t* src64 = nullptr;
     int64_t n = 0;
     switch (item) {
     case DMT_MSC_CRIT0: case DMT_MSC_CRIT1: case DMT_MSC_CRIT2: case DMT_MSC_CRIT3:
-        src32 = P<int>(c->crit[item]); n = c->ncrit[item]; break;
+        src32 = P<int>(m.crit[item]); n = m.ncrit[item]; break;
     case DMT_MSC_DESC_SADDLE:
-        n = c->n_desc;
+        n = m.n_desc;
         if (n > cap) return fail(c, DMT_E_INVALID, "destination too small");
         if (n) {
-            k_desc_saddles<<<nblocks(n), TPB, 0, st>>>(P<int>(c->crit[1]), n, dst);
+            k_desc_saddles<<<nblocks(n), TPB, 0, st>>>(P<int>(m.crit[1]), n, dst);
             CHECK_LAUNCH(c);
             HIPCHK(c, hipStreamSynchronize(st));
         }
         return DMT_OK;
-    case DMT_MSC_DESC_OFFSETS: src64 = P<int64_t>(c->doff); n = c->n_desc + 1; break;
-    case DMT_MSC_DESC_CELLS: src32 = P<int>(c->dcell); n = c->n_desc_cells; break;
-    case DMT_MSC_DESC_TERMINAL: src32 = P<int>(c->dterm); n = c->n_desc; break;
-    case DMT_MSC_ASC_SADDLE: src32 = P<int>(c->asad); n = c->n_asc; break;
-    case DMT_MSC_ASC_OFFSETS: src64 = P<int64_t>(c->aoff); n = c->n_asc + 1; break;
-    case DMT_MSC_ASC_CELLS: src32 = P<int>(c->acell); n = c->n_asc_cells; break;
-    case DMT_MSC_ASC_TERMINAL: src32 = P<int>(c->aterm); n = c->n_asc; break;
-    case DMT_MSC_MIN_LABEL: src32 = P<int>(c->vlab); n = c->n_vlab; break;
-    case DMT_MSC_MAX_LABEL: src32 = P<int>(c->tlab); n = c->n_tlab; break;
+    case DMT_MSC_DESC_OFFSETS: src64 = P<int64_t>(m.doff); n = m.n_desc + 1; break;
+    case DMT_MSC_DESC_CELLS: src32 = P<int>(m.dcell); n = m.n_desc_cells; break;
+    case DMT_MSC_DESC_TERMINAL: src32 = P<int>(m.dterm); n = m.n_desc; break;
+    case DMT_MSC_ASC_SADDLE: src32 = P<int>(m.asad); n = m.n_asc; break;
+    case DMT_MSC_ASC_OFFSETS: src64 = P<int64_t>(m.aoff); n = m.n_asc + 1; break;
+    case DMT_MSC_ASC_CELLS: src32 = P<int>(m.acell); n = m.n_asc_cells; break;
+    case DMT_MSC_ASC_TERMINAL: src32 = P<int>(m.aterm); n = m.n_asc; break;
+    case DMT_MSC_MIN_LABEL: src32 = P<int>(m.vlab); n = m.n_vlab; break;
+    case DMT_MSC_MAX_LABEL: src32 = P<int>(m.tlab); n = m.n_tlab; break;
     default: return fail(c, DMT_E_INVALID, "unknown item");
     }
     if (n > cap) return fail(c, DMT_E_INVALID, "destination too small");
@@ -781,19 +937,55 @@ dmt_status dmt_correct(dmt_context* c, const dmt_grid* gr, const float* f, const
                        const dmt_options* o, float* g_out, uint8_t* q_out, dmt_stats* stats, hipStream_t st) {
     if (!c) return DMT_E_INVALID;
     if (!f || !g_hat || !o || !g_out || !q_out) return fail(c, DMT_E_INVALID, "null argument");
-    Dims dm;
-    int D;
-    dmt_status s = check_grid(c, gr, dm, D);
-    if (s != DMT_OK) return s;
-    if (o->tier < 1 || o->tier > 4) return fail(c, DMT_E_INVALID, "tier must be 1..4");
-    if (o->q_max < 0 || o->q_max > 7) return fail(c, DMT_E_INVALID, "q_max must be 0..7");
-    if (o->flags & ~(uint32_t)(DMT_F_DENSE | DMT_F_PHASES)) return fail(c, DMT_E_INVALID, "unknown flags");
-    if (!(xi > 0.0f) || !std::isfinite(xi)) return fail(c, DMT_E_INVALID, "xi must be finite and > 0");
-    if (!(ldexpf(xi, -o->q_max) >= FLT_MIN)) return fail(c, DMT_E_INVALID, "xi / 2^q_max is not a normal float");
+    std::vector<Job> jobs(1);
+    Job& J = jobs[0];
+    TRY(check_grid(c, gr, J.dm, J.D));
+    TRY(check_options(c, o, xi));
     HIPCHK(c, hipSetDevice(c->device));
+    J.f = f; J.gh = g_hat; J.xi = xi; J.o = *o; J.g_out = g_out; J.q_out = q_out;
     c->n_lossless = 0;
-    return D == 2 ? correct_impl<2>(c, dm, f, g_hat, xi, o, g_out, q_out, stats, st)
-                  : correct_impl<3>(c, dm, f, g_hat, xi, o, g_out, q_out, stats, st);
+    c->log.clear();
+    TRY(run_jobs(c, jobs, true, st));
+    if (J.status == DMT_E_NONFINITE) return fail(c, DMT_E_NONFINITE, "non-finite value in f or g_hat");
+    if (J.status == DMT_E_BOUND) return fail(c, DMT_E_BOUND, "|g_hat - f| > xi somewhere");
+    if (stats) *stats = J.stats;
+    return J.status;
+}
+
+dmt_status dmt_correct_batch(dmt_context* c, int32_t n_jobs, dmt_job* jobs_host, hipStream_t st) {
+    if (!c) return DMT_E_INVALID;
+    if (n_jobs < 0 || (n_jobs > 0 && !jobs_host)) return fail(c, DMT_E_INVALID, "bad job list");
+    if (n_jobs == 0) return DMT_OK;
+    HIPCHK(c, hipSetDevice(c->device));
+    std::vector<Job> jobs;
+    std::vector<int> idx;
+    for (int j = 0; j < n_jobs; j++) {
+        dmt_job& h = jobs_host[j];
+        h.stats = dmt_stats{};
+        Job J;
+        dmt_status s = check_grid(c, &h.grid, J.dm, J.D);
+        if (s == DMT_OK) s = check_options(c, &h.opts, h.xi);
+        if (s == DMT_OK && h.opts.flags != 0) s = fail(c, DMT_E_INVALID, "batched jobs take no flags");
+        if (s == DMT_OK && (!h.f || !h.g_hat || !h.g_out || !h.q_out)) s = fail(c, DMT_E_INVALID, "null argument");
+        h.status = s;
+        if (s != DMT_OK) continue;
+        J.f = h.f; J.gh = h.g_hat; J.xi = h.xi; J.o = h.opts; J.g_out = h.g_out; J.q_out = h.q_out;
+        jobs.push_back(J);
+        idx.push_back(j);
+    }
+    if (!jobs.empty()) TRY(run_jobs(c, jobs, false, st));
+    for (size_t k = 0; k < jobs.size(); k++) {
+        jobs_host[idx[k]].status = jobs[k].status;
+        jobs_host[idx[k]].stats = jobs[k].stats;
+    }
+    // the call's status: the first error of any job, else not-converged if any, else ok
+    dmt_status worst = DMT_OK;
+    for (int j = 0; j < n_jobs; j++) {
+        const dmt_status s = jobs_host[j].status;
+        if (s < 0 && worst >= 0) worst = s;
+        else if (s == DMT_W_NOT_CONVERGED && worst == DMT_OK) worst = s;
+    }
+    return worst;
 }
 
 dmt_status dmt_lossless_edits(dmt_context* c, int64_t* idx_out, float* val_out, int64_t cap, int64_t* count,
@@ -845,11 +1037,11 @@ dmt_status dmt_profile_read(dmt_context* c, int kernel, int64_t* launches, doubl
     *launches = (int64_t)c->prof_ev[kernel].size();
     *ms_total = ms;
     *units = c->prof_units[kernel];
-    if (kernel >= DMT_PROF_LOOP_GRAD && kernel <= DMT_PROF_LOOP_APPLY) {
+    if (kernel >= DMT_PROF_LOOP_SAPPLY && kernel <= DMT_PROF_LOOP_VR) {
         // phases inside the persistent loop: wall-clock ticks (100 MHz) recorded by the kernel
         *launches = 0;
         *units = 0;
-        *ms_total = c->ctl.p ? (double)c->hctl->ph[kernel - DMT_PROF_LOOP_GRAD] * 1e-5 : 0.0;
+        *ms_total = (double)c->hbctl->ph[kernel - DMT_PROF_LOOP_SAPPLY] * 1e-5;
     }
     return DMT_OK;
 }

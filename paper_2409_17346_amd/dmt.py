@@ -37,13 +37,12 @@ MSC_ITEMS = {
 ABI_SYMBOLS = [
     "dmt_context_create", "dmt_context_destroy", "dmt_last_error", "dmt_cell_id_space",
     "dmt_xi_from_relative", "dmt_bounds", "dmt_gradient_pairs", "dmt_extract_msc", "dmt_msc_copy",
-    "dmt_correct", "dmt_lossless_edits", "dmt_iteration_log", "dmt_apply_edits", "dmt_profile_enable",
-    "dmt_profile_read",
+    "dmt_correct", "dmt_correct_batch", "dmt_lossless_edits", "dmt_iteration_log", "dmt_apply_edits",
+    "dmt_profile_enable", "dmt_profile_read",
 ]
 
 PROF_KERNELS = {"gradient": 0, "classify": 1, "apply": 2, "sstep": 3, "setup": 4, "msc": 5, "loop": 6,
-                "loop.grad": 7, "loop.vmask": 8, "loop.requests": 9, "loop.scheck": 10, "loop.stargets": 11,
-                "loop.apply": 12}
+                "loop.sapply": 7, "loop.grad": 8, "loop.vr": 9}
 
 
 class DmtError(RuntimeError):
@@ -67,6 +66,12 @@ class dmt_stats(C.Structure):
 
     def as_dict(self) -> Dict[str, int]:
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+class dmt_job(C.Structure):
+    _fields_ = [("grid", dmt_grid), ("f", C.c_void_p), ("g_hat", C.c_void_p), ("xi", C.c_float),
+                ("opts", dmt_options), ("g_out", C.c_void_p), ("q_out", C.c_void_p), ("status", C.c_int),
+                ("stats", dmt_stats)]
 
 
 _lib = None
@@ -94,6 +99,7 @@ def load_library(path: str = SO):
     L.dmt_msc_copy.argtypes = [VP, C.c_int, VP, C.c_int64, VP]
     L.dmt_correct.argtypes = [VP, C.POINTER(dmt_grid), VP, VP, C.c_float, C.POINTER(dmt_options), VP, VP,
                               C.POINTER(dmt_stats), VP]
+    L.dmt_correct_batch.argtypes = [VP, C.c_int32, C.POINTER(dmt_job), VP]
     L.dmt_lossless_edits.argtypes = [VP, VP, VP, C.c_int64, P64, VP]
     L.dmt_iteration_log.argtypes = [VP, P64, C.c_int64, P64]
     L.dmt_apply_edits.argtypes = [VP, VP, VP, C.c_int64, VP, VP, C.c_int64, C.c_float, C.c_int32, VP, VP]
@@ -251,6 +257,43 @@ def dmt_correct(ctx: Context, f: torch.Tensor, g_hat: torch.Tensor, xi: float, t
         idx, val = dmt_lossless_edits(ctx, f.device)
         log = dmt_iteration_log(ctx)
     return Result(STATUS_NAMES[rc], g_out, q_out, stats, idx, val, log)
+
+
+def dmt_correct_batch(ctx: Context, fields, tier: int = 4, q_max: int = 6, max_iters: int = -1,
+                      outputs=None):
+    """Corrects a list of (f, g_hat, xi) jobs together.  Returns a list of Result (lossless edits
+    derived from q == 0xFF; no per-iteration log)."""
+    n = len(fields)
+    arr = (dmt_job * n)()
+    outs = []
+    for j, (f, gh, xi) in enumerate(fields):
+        _dev(f)
+        _dev(gh)
+        if outputs is None:
+            g_out = torch.empty_like(f)
+            q_out = torch.empty(f.shape, dtype=torch.uint8, device=f.device)
+        else:
+            g_out, q_out = outputs[j]
+        outs.append((g_out, q_out))
+        arr[j].grid = grid_of(f)
+        arr[j].f = f.data_ptr()
+        arr[j].g_hat = gh.data_ptr()
+        arr[j].xi = xi
+        arr[j].opts = dmt_options(tier, q_max, max_iters, 0)
+        arr[j].g_out = g_out.data_ptr()
+        arr[j].q_out = q_out.data_ptr()
+    st = _stream(fields[0][0]) if n else None
+    rc = ctx.L.dmt_correct_batch(ctx.h, n, arr, st)
+    if rc < 0 and all(arr[j].status >= 0 for j in range(n)):
+        raise DmtError(rc, ctx.L.dmt_last_error(ctx.h).decode())
+    res = []
+    for j in range(n):
+        g_out, q_out = outs[j]
+        stj = int(arr[j].status)
+        idx = torch.nonzero(q_out.reshape(-1) == 0xFF).reshape(-1) if stj >= 0 else None
+        val = g_out.reshape(-1)[idx] if stj >= 0 else None
+        res.append(Result(STATUS_NAMES.get(stj, str(stj)), g_out, q_out, arr[j].stats.as_dict(), idx, val, None))
+    return res
 
 
 def dmt_lossless_edits(ctx: Context, device) -> Tuple[torch.Tensor, torch.Tensor]:

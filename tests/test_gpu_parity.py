@@ -212,3 +212,52 @@ def test_identity_and_errors(ctx, dmt):
     with pytest.raises(dmt.DmtError) as e:
         dmt.dmt_correct(ctx, f[:1], f[:1], w.xi)
     assert e.value.status == -1
+
+
+# ------------------------------------------------------------------------------------------
+# Batched correction: every job equals the oracle and the single-field call
+
+def _batch_jobs():
+    jobs = []
+    for i, (shape, kind, ghat, rel) in enumerate(CORR_CASES):
+        jobs.append(synth.tiny_cases(30 + i, shape, rel=rel, kind=kind, ghat=ghat))
+    jobs.append(synth.config_small2d())
+    w = synth.config_large2d()
+    w.f = np.ascontiguousarray(w.f[:96, :160])
+    w.g_hat = np.ascontiguousarray(w.g_hat[:96, :160])
+    jobs.append(w)
+    jobs.append(synth.config_atoms3d(seed=5, side=24, n_atoms=8))
+    return jobs
+
+
+@pytest.mark.parametrize("tier", [2, 4])
+def test_correct_batch_matches_oracle_and_single(ctx, dmt, tier):
+    ws = _batch_jobs()
+    fields = [(_t(w.f), _t(w.g_hat), w.xi) for w in ws]
+    res = dmt.dmt_correct_batch(ctx, fields, tier=tier, q_max=6)
+    for w, r in zip(ws, res):
+        nx, ny, nz = w.dims
+        o = oracle.correct(oracle.Complex.grid(nx, ny, nz), w.f.reshape(-1), w.g_hat.reshape(-1), w.xi, tier, 6)
+        assert r.status == o["status"], w.name
+        for k, v in o["stats"].items():
+            if k != "status":
+                assert r.stats[k] == v, (w.name, k)
+        assert np.array_equal(r.g.cpu().numpy().reshape(-1).view(np.uint32), o["g"].view(np.uint32)), w.name
+        assert np.array_equal(r.q.cpu().numpy().reshape(-1), o["q"]), w.name
+        assert np.array_equal(r.lossless_idx.cpu().numpy(), o["lossless_idx"]), w.name
+        s = dmt.dmt_correct(ctx, _t(w.f), _t(w.g_hat), w.xi, tier, 6)
+        assert torch.equal(s.g.view(torch.int32), r.g.view(torch.int32)) and torch.equal(s.q, r.q)
+
+
+def test_correct_batch_isolates_bad_jobs(ctx, dmt):
+    good = synth.tiny_cases(3, (20, 18), rel=0.1, kind="uniform")
+    bad = synth.tiny_cases(4, (9, 9), rel=0.1, kind="uniform")
+    fields = [(_t(good.f), _t(good.g_hat), good.xi), (_t(bad.f), _t(bad.f) + 1.0, bad.xi),
+              (_t(good.f), _t(good.g_hat), good.xi)]
+    res = dmt.dmt_correct_batch(ctx, fields)
+    assert res[1].status == "bound"
+    nx, ny, nz = good.dims
+    o = oracle.correct(oracle.Complex.grid(nx, ny, nz), good.f.reshape(-1), good.g_hat.reshape(-1), good.xi, 4, 6)
+    for r in (res[0], res[2]):
+        assert r.status == o["status"]
+        assert np.array_equal(r.g.cpu().numpy().reshape(-1).view(np.uint32), o["g"].view(np.uint32))
