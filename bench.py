@@ -100,6 +100,9 @@ def main():
     ap.add_argument("--cpu-crop", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--flags", type=int, default=0, help="dmt_options.flags (1 dense loop, 2 one launch per phase)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first copy a buffer of this many MiB once (untimed): the reference kernel that scales "
+                         "profiler byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the correction of one field runs on one "
@@ -111,6 +114,12 @@ def main():
 
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
+    if args.copy_probe_mib > 0:
+        src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)   # an elementwise kernel: reads and writes copy_probe_mib MiB
+        torch.cuda.synchronize()
+        del src, dst
     w = workload(args.workload)
     print(f"[bench] workload {w.name} shape {w.f.shape} xi {w.xi:.6g}", file=sys.stderr, flush=True)
     ctx = dmt.Context(0)
