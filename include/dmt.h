@@ -80,8 +80,8 @@ typedef struct {
 /* Option flags (results are bit-identical in every form; they exist for testing):
  * DMT_F_DENSE   recompute the whole gradient and every violation each iteration instead of only
  *               around the vertices edited in the previous iteration;
- * DMT_F_PHASES  run the loop as one kernel launch per phase instead of one persistent
- *               cooperative kernel. */
+ * DMT_F_PHASES  run every iteration as full-grid kernel launches, one per phase, instead of
+ *               inside one workgroup that stays resident for the whole loop. */
 #define DMT_F_DENSE 1u
 #define DMT_F_PHASES 2u
 
@@ -99,8 +99,12 @@ typedef struct {
 
 /* Per-iteration log record (int64 each): kind (1 = C, 2 = S), FP0, FN0, FP1, FN1, FP2, FN2,
  * FP3, FN3 (false positive / negative critical cells by dimension), TM_desc, TM_asc
- * (troublemaker branches fixed), n_req (vertices requested), changed, 0, 0, 0. */
-#define DMT_LOG_WORDS 16
+ * (troublemaker branches fixed), n_req (vertices requested), changed (vertices edited), then
+ * the work of the frontier forms in that iteration (0 in the dense form): dirty vertices,
+ * affected anchors, listed violating anchors, branches whose first differing cell was
+ * settled, branch cells examined while settling them, branch cells touched, and the duration
+ * of the iteration in the resident loop in 10 ns ticks (0 elsewhere; timing, not a result). */
+#define DMT_LOG_WORDS 20
 
 /* ---- context ----------------------------------------------------------------------------- */
 
@@ -186,9 +190,10 @@ typedef struct {
     dmt_stats stats;
 } dmt_job;
 
-/* Corrects n_jobs independent fields of any sizes (2D and 3D mixed) together: their C/S loops
- * run in lockstep inside one persistent kernel, so each grid-wide synchronisation serves every
- * unfinished field.  Every job's outputs equal those of dmt_correct on the same inputs.  A job
+/* Corrects n_jobs independent fields of any sizes (2D and 3D mixed) together: after each
+ * field's setup and dense first iteration, one launch runs the C/S loops, each field inside one
+ * workgroup taken from a queue, so fields proceed concurrently on different compute units.
+ * Every job's outputs equal those of dmt_correct on the same inputs.  A job
  * that fails validation gets its error status and is skipped; the others still run.  Returns
  * the first job error, else DMT_W_NOT_CONVERGED if any job did not converge, else DMT_OK.  The
  * lossless edits of a job are the vertices whose q_out is 0xFF, with values g_out; no
@@ -215,15 +220,15 @@ dmt_status dmt_apply_edits(dmt_context *ctx, const float *g_hat, const uint8_t *
 /* Kernel families timed by dmt_profile_*: */
 enum {
     DMT_PROF_GRADIENT = 0,  /* lower-star gradient pass, units = vertices */
-    DMT_PROF_CLASSIFY = 1,  /* critical-cell violation pass, units = anchors */
+    DMT_PROF_CLASSIFY = 1,  /* critical-cell violation pass over every anchor, units = anchors */
     DMT_PROF_APPLY = 2,     /* Equation 2 edit pass, units = vertices */
     DMT_PROF_SSTEP = 3,     /* separatrix troublemaker pass, units = branch cells */
     DMT_PROF_SETUP = 4,     /* floors and validation, units = vertices */
     DMT_PROF_MSC = 5,       /* critical cells + separatrix branches of f, units = vertices */
-    DMT_PROF_LOOP = 6,      /* the frontier correction loop (persistent kernel or its phases) */
-    /* phases inside the persistent loop kernel of the last dmt_correct (wall clock of block 0,
-     * including the grid barrier that ends each phase; launches and units read 0): the
-     * troublemaker pass, the gradient pass and the violation pass */
+    DMT_PROF_LOOP = 6,      /* the frontier correction loop (resident kernel or its phases) */
+    /* phases inside the resident loop kernel during the last correction call, summed over jobs
+     * (wall clock of each job's workgroup, including the workgroup barrier that ends each phase;
+     * launches and units read 0): the troublemaker pass, the gradient pass and the violation pass */
     DMT_PROF_LOOP_SAPPLY = 7, DMT_PROF_LOOP_GRAD = 8, DMT_PROF_LOOP_VR = 9,
     DMT_PROF_KERNELS = 10
 };

@@ -28,8 +28,10 @@ namespace dmt {
 // readers belong to iteration it-2).  List buffers alternate by iteration parity.
 struct Slot {
     unsigned long long cnt[CNT_WORDS];  // log record layout
-    int n_req;              // distinct vertices requested in this iteration
     int n_dv, n_da, n_vl;   // dirty vertices, affected anchors, violation list of this iteration
+    int n_tc;               // branch cells of f on a dirty vertex (touched this iteration)
+    int n_db;               // branches with a touched cell
+    int n_scan;             // branch cells examined to settle those branches
 };
 
 struct Ctl {
@@ -37,36 +39,82 @@ struct Ctl {
     int done;               // 0 running, 1 converged, 2 iteration cap, 3 stalled, 4 paused (log full)
     int c_it, s_it;
     long long residual;
+    unsigned long long ph[3];   // wall-clock ticks in the resident loop: troublemaker, gradient, violation passes
     Slot slot[3];
 };
 
-struct FrontierBufs {
-    Ctl* ctl;
-    const float *f, *gh, *lo;
-    float* gb[2];           // g^(k) in gb[k & 1]
-    uint8_t* state;
-    const uint8_t* fpl;
-    uint8_t* gpl;
-    uint32_t* vmask;        // violating planes per anchor
-    int* vl[2];             // violation anchor lists
-    int* dvl[2];            // dirty vertex lists
-    int* dal[2];            // affected anchor lists
-    unsigned* vstamp;       // dirty-vertex stamps
-    unsigned* astamp[2];    // affected-anchor stamps by iteration parity (iteration k's in [k & 1]: the
-                            // edits of iteration k mark [(k+1) & 1] while [k & 1] is still read)
-    unsigned* rstamp;       // request stamps
-    long long* log;         // DMT_LOG_WORDS per iteration
-    // separatrix branches of f
-    const int *dcell, *dcbr, *dterm, *acell, *acbr, *aterm;
-    const int64_t *doff, *aoff;
-    int* dfirst;
-    int* afirst;
-    long long n_dcell, n_acell;
-    int n_desc, n_asc;
-    float delta;
-    int q_max, tier;
+// Buffers of one job.  The host fills FrontierBufs (plain pointers); device code reads the same
+// bytes as a FrontierView, whose pointers carry the global address space in the device pass, so
+// accesses through them compile to global rather than flat instructions even when the structure
+// is read from memory.  Both are generated from one field list and have one layout.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define DMT_GPTR(T) __attribute__((address_space(1))) T*
+#else
+#define DMT_GPTR(T) T*
+#endif
+#define DMT_PTR(T) T*
+
+#define DMT_FRONTIER_FIELDS(P)                                                                     \
+    P(Ctl) ctl;                                                                                    \
+    P(const float) f;                                                                              \
+    P(const float) gh;                                                                             \
+    P(const float) lo;                                                                             \
+    P(float) gb[2];           /* g^(k) in gb[k & 1] */                                             \
+    P(uint8_t) state;                                                                              \
+    P(const uint8_t) fpl;                                                                          \
+    P(uint8_t) gpl;                                                                                \
+    P(uint32_t) vmask;        /* violating planes per anchor */                                    \
+    P(int) vl[2];             /* violation anchor lists */                                         \
+    P(int) dvl[2];            /* dirty vertex lists */                                             \
+    P(int) dal[2];            /* affected anchor lists */                                          \
+    P(unsigned) vstamp;       /* dirty-vertex stamps */                                            \
+    /* affected-anchor stamps by iteration parity: iteration k's in [k & 1]; the edits of         \
+       iteration k mark [(k+1) & 1] while [k & 1] is still read */                                 \
+    P(unsigned) astamp[2];                                                                         \
+    P(unsigned) rstamp;       /* request stamps */                                                 \
+    P(long long) log;         /* DMT_LOG_WORDS per iteration */                                    \
+    int log_cap;              /* records log can hold */                                           \
+    int ndim;                 /* 2 or 3 */                                                         \
+    Dims dm;                                                                                       \
+    /* separatrix branches of f */                                                                 \
+    P(const int) dcell;                                                                            \
+    P(const int) dcbr;                                                                             \
+    P(const int) dterm;                                                                            \
+    P(const int) acell;                                                                            \
+    P(const int) acbr;                                                                             \
+    P(const int) aterm;                                                                            \
+    P(const int64_t) doff;                                                                         \
+    P(const int64_t) aoff;                                                                         \
+    P(int) dfirst;            /* first cell of each branch whose g pairing differs (INF32: none) */ \
+    P(int) afirst;                                                                                 \
+    long long n_dcell, n_acell;                                                                    \
+    int n_desc, n_asc;                                                                             \
+    /* vertex -> branch cells containing it, CSR: entries vstart[v] .. vstart[v+1] of ecell, each \
+       a branch cell index (descending k, ascending n_dcell + k); branch ids: descending b,        \
+       ascending n_desc + b */                                                                     \
+    P(const int) vstart;                                                                           \
+    P(const int) ecell;                                                                            \
+    P(unsigned) bstamp;       /* touched-branch stamps */                                          \
+    P(int) tcl;               /* touched cells of the current iteration */                         \
+    P(int) dbl;               /* touched branches of the current iteration */                      \
+    P(int) newmin;            /* per branch id: first touched cell that differs (INF32 between) */ \
+    float delta;                                                                                   \
+    int q_max, tier;                                                                               \
     long long max_iters;
+
+struct FrontierBufs {
+    DMT_FRONTIER_FIELDS(DMT_PTR)
 };
+
+struct FrontierView {
+    DMT_FRONTIER_FIELDS(DMT_GPTR)
+};
+
+static_assert(sizeof(FrontierView) == sizeof(FrontierBufs), "one layout");
+
+__device__ __forceinline__ const FrontierView& view(const FrontierBufs& b) {
+    return *reinterpret_cast<const FrontierView*>(&b);
+}
 
 __device__ __forceinline__ int ld_relaxed(const int* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -87,7 +135,33 @@ __device__ __forceinline__ int wave_append(bool pred, int* counter) {
     return base + __popcll(b & ((1ull << lane) - 1ull));
 }
 
-__device__ __forceinline__ Slot& slot_of(const FrontierBufs& B, int it) { return B.ctl->slot[it % 3]; }
+// Reserves k slots per lane (k >= 0), one atomic per wave; whole waves call it.  Returns the
+// lane's first index (unspecified when the wave reserves nothing).
+__device__ __forceinline__ int wave_append_n(int k, int* counter) {
+    const int lane = __lane_id();
+    int incl = k;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += t;
+    }
+    const int total = __shfl(incl, 63, 64);
+    int base = 0;
+    if (total != 0) {
+        if (lane == 63) base = atomicAdd(counter, total);
+        base = __shfl(base, 63, 64);
+    }
+    return base + incl - k;
+}
+
+// Lists are walked in rounds of gsize items, item base + gtid in a round; a wave whose first
+// item lies past the end leaves the loop (a wave-uniform test, so wave-level collectives in the
+// body stay safe), which keeps idle waves from competing with working ones for issue slots.
+__device__ __forceinline__ bool wave_done(int base, int gtid, int n) {
+    return base + (gtid & ~63) >= n;
+}
+
+__device__ __forceinline__ Slot& slot_of(const FrontierView& B, int it) { return B.ctl->slot[it % 3]; }
 
 __device__ __forceinline__ unsigned long long c_total(const Slot& s) {
     unsigned long long t = 0;
@@ -97,7 +171,7 @@ __device__ __forceinline__ unsigned long long c_total(const Slot& s) {
 }
 
 // Violations of iteration it: critical-cell violations, else (tier >= 3) troublemakers.
-__device__ __forceinline__ unsigned long long violations(const FrontierBufs& B, int it) {
+__device__ __forceinline__ unsigned long long violations(const FrontierView& B, int it) {
     const Slot& s = slot_of(B, it);
     const unsigned long long ct = c_total(s);
     if (ct) return ct;
@@ -106,12 +180,11 @@ __device__ __forceinline__ unsigned long long violations(const FrontierBufs& B, 
 
 // ---- Equation 2 on one vertex, and the neighbourhood an edit makes dirty -------------------
 
-__device__ __forceinline__ bool apply_vertex(const FrontierBufs& B, int v, int it) {
-    const uint8_t st = B.state[v];
+// Equation 2 on vertex v given its state byte st, g_hat and floor (loaded by the caller).
+__device__ __forceinline__ bool apply_vertex(const FrontierView& B, int v, int it, uint8_t st, float ghv, float l) {
     if (st & 0x80) return false;
     const int q = st & 7;
-    const float t = fmaf(-(float)(q + 1), B.delta, B.gh[v]);
-    const float l = B.lo[v];
+    const float t = fmaf(-(float)(q + 1), B.delta, ghv);
     float* gn = B.gb[(it + 1) & 1];
     if (q < B.q_max && t >= l) {
         B.state[v] = (uint8_t)(q + 1);
@@ -124,58 +197,94 @@ __device__ __forceinline__ bool apply_vertex(const FrontierBufs& B, int v, int i
 }
 
 // Marks the closed 1-ring of an edited vertex as dirty and the anchors of cells touching it as
-// affected, for iteration it + 1.  Lanes without an edit pass changed = false.
+// affected, for iteration it + 1.  Lanes without an edit pass changed = false; whole waves
+// call it.  The stamps are claimed without branches between the atomics (a neighbour outside
+// the grid issues a maximum with 0 on the edited vertex's own entry, which changes nothing, and
+// its result is discarded), so all of them are in flight at once; the winners are then
+// appended with one atomic per list and wave.
 template <int D>
-__device__ __noinline__ void mark_neighbourhood(const FrontierBufs& B, const Dims& dm, bool changed, int v,
+__device__ __forceinline__ void mark_neighbourhood(const FrontierView& B, const Dims& dm, bool changed, int v,
                                                    int it) {
     constexpr auto& g = G<D>::g;
+    constexpr int NV = Geom<D>::NS + 1;
     if (__ballot(changed) == 0) return;
     const int nxt = (it + 1) & 1;
     Slot& N1 = slot_of(B, it + 1);
     const unsigned stamp = (unsigned)it + 1u;
+    uint32_t mv = 0;
+    uint64_t ma = 0;
     int x = 0, y = 0, z = 0;
-    if (changed) coords(dm, v, x, y, z);
+    if (changed) {
+        coords(dm, v, x, y, z);
+        unsigned* vs = B.vstamp;
+        unsigned* as = B.astamp[nxt];
+        unsigned ov[NV];
+        unsigned oa[g.naff];
+        uint32_t okv = 0;
+        uint64_t oka = 0;
 #pragma unroll
-    for (int s = -1; s < Geom<D>::NS; s++) {
-        const int dx = s < 0 ? 0 : g.slot_d[s < 0 ? 0 : s][0];
-        const int dy = s < 0 ? 0 : g.slot_d[s < 0 ? 0 : s][1];
-        const int dz = s < 0 ? 0 : g.slot_d[s < 0 ? 0 : s][2];
-        bool mine = false;
-        int t = 0;
-        if (changed && (unsigned)(x + dx) < (unsigned)dm.nx && (unsigned)(y + dy) < (unsigned)dm.ny &&
-            (unsigned)(z + dz) < (unsigned)dm.nz) {
-            t = v + dx + dm.nx * dy + dm.nxy * dz;
-            mine = atomicMax(&B.vstamp[t], stamp) < stamp;
+        for (int s = 0; s < NV; s++) {
+            const int dx = s == 0 ? 0 : g.slot_d[s == 0 ? 0 : s - 1][0];
+            const int dy = s == 0 ? 0 : g.slot_d[s == 0 ? 0 : s - 1][1];
+            const int dz = s == 0 ? 0 : g.slot_d[s == 0 ? 0 : s - 1][2];
+            const bool ok = (unsigned)(x + dx) < (unsigned)dm.nx && (unsigned)(y + dy) < (unsigned)dm.ny &&
+                            (unsigned)(z + dz) < (unsigned)dm.nz;
+            okv |= (uint32_t)ok << s;
+            ov[s] = atomicMax(vs + (ok ? v + dx + dm.nx * dy + dm.nxy * dz : v), ok ? stamp : 0u);
         }
-        const int idx = wave_append(mine, &N1.n_dv);
-        if (mine) B.dvl[nxt][idx] = t;
+#pragma unroll
+        for (int j = 0; j < g.naff; j++) {
+            const int dx = g.aff_d[j][0], dy = g.aff_d[j][1], dz = g.aff_d[j][2];
+            const bool ok = x + dx >= 0 && y + dy >= 0 && z + dz >= 0 && x + dx < dm.nx && y + dy < dm.ny &&
+                            z + dz < dm.nz;
+            oka |= (uint64_t)ok << j;
+            oa[j] = atomicMax(as + (ok ? v + dx + dm.nx * dy + dm.nxy * dz : v), ok ? stamp : 0u);
+        }
+#pragma unroll
+        for (int s = 0; s < NV; s++)
+            if (((okv >> s) & 1u) && ov[s] < stamp) mv |= 1u << s;
+#pragma unroll
+        for (int j = 0; j < g.naff; j++)
+            if (((oka >> j) & 1ull) && oa[j] < stamp) ma |= 1ull << j;
+    }
+    int iv = wave_append_n(__popc(mv), &N1.n_dv);
+    int ia = wave_append_n(__popcll(ma), &N1.n_da);
+    if (!changed) return;
+    int* dv = B.dvl[nxt];
+    int* da = B.dal[nxt];
+#pragma unroll
+    for (int s = 0; s < NV; s++) {
+        if (mv & (1u << s)) {
+            const int dx = s == 0 ? 0 : g.slot_d[s == 0 ? 0 : s - 1][0];
+            const int dy = s == 0 ? 0 : g.slot_d[s == 0 ? 0 : s - 1][1];
+            const int dz = s == 0 ? 0 : g.slot_d[s == 0 ? 0 : s - 1][2];
+            dv[iv++] = v + dx + dm.nx * dy + dm.nxy * dz;
+        }
     }
 #pragma unroll
     for (int j = 0; j < g.naff; j++) {
-        const int dx = g.aff_d[j][0], dy = g.aff_d[j][1], dz = g.aff_d[j][2];
-        bool mine = false;
-        int a = 0;
-        if (changed && x + dx >= 0 && y + dy >= 0 && z + dz >= 0 && x + dx < dm.nx && y + dy < dm.ny &&
-            z + dz < dm.nz) {
-            a = v + dx + dm.nx * dy + dm.nxy * dz;
-            mine = atomicMax(&B.astamp[nxt][a], stamp) < stamp;
-        }
-        const int idx = wave_append(mine, &N1.n_da);
-        if (mine) B.dal[nxt][idx] = a;
+        if (ma & (1ull << j)) da[ia++] = v + g.aff_d[j][0] + dm.nx * g.aff_d[j][1] + dm.nxy * g.aff_d[j][2];
     }
 }
 
-// Request of vertex v (v < 0: none) in iteration it: the first requester counts it and, when
-// edits are allowed, edits it and marks its neighbourhood.
+// Request of vertex v (v < 0: none) in iteration it: the first requester counts it in rc[0]
+// and, when edits are allowed, edits it (counted in rc[1]) and marks its neighbourhood.
 template <int D>
-__device__ __noinline__ void request_apply(const FrontierBufs& B, const Dims& dm, int v, int it, bool edit,
-                                              int* changed_cnt) {
+__device__ __forceinline__ void request_apply(const FrontierView& B, const Dims& dm, int v, int it, bool edit,
+                                              int* rc) {
     const unsigned stamp = (unsigned)it + 1u;
-    const bool mine = v >= 0 && atomicMax(&B.rstamp[v], stamp) < stamp;
-    wave_append(mine, &slot_of(B, it).n_req);
     bool changed = false;
-    if (mine && edit) changed = apply_vertex(B, v, it);
-    if (changed) (*changed_cnt)++;
+    if (v >= 0) {
+        // the vertex's state, g_hat and floor are read while the stamp atomic is in flight (only
+        // the stamp winner edits v, so they are current whenever they are used)
+        const uint8_t st = B.state[v];
+        const float ghv = B.gh[v], l = B.lo[v];
+        if (atomicMax(&B.rstamp[v], stamp) < stamp) {
+            rc[0]++;
+            if (edit) changed = apply_vertex(B, v, it, st, ghv, l);
+            if (changed) rc[1]++;
+        }
+    }
     mark_neighbourhood<D>(B, dm, changed, v, it);
 }
 
@@ -197,7 +306,7 @@ __device__ __forceinline__ void vmask_plane(const Dims& dm, int a, int x, int y,
 // ---- target of one violating plane (Rules A and B, as classify_plane) ---------------------
 
 template <int D, int P>
-__device__ __forceinline__ int plane_target(const FrontierBufs& B, const Dims& dm, int a, const float* gcur, int* cnt) {
+__device__ __forceinline__ int plane_target(const FrontierView& B, const Dims& dm, int a, const float* gcur, int* cnt) {
     constexpr auto& g = G<D>::g;
     constexpr int dim = g.bdim[P];
     const uint8_t fc = B.fpl[(size_t)P * dm.n + a];
@@ -239,7 +348,7 @@ __device__ __forceinline__ int plane_target(const FrontierBufs& B, const Dims& d
 
 // plane p chosen at run time
 template <int D, int P>
-__device__ __forceinline__ int plane_target_dyn(int p, const FrontierBufs& B, const Dims& dm, int a, const float* gcur,
+__device__ __forceinline__ int plane_target_dyn(int p, const FrontierView& B, const Dims& dm, int a, const float* gcur,
                                                 int* cnt) {
     if (p == P) return plane_target<D, P>(B, dm, a, gcur, cnt);
     if constexpr (P + 1 < Geom<D>::NB) return plane_target_dyn<D, P + 1>(p, B, dm, a, gcur, cnt);
@@ -249,8 +358,8 @@ __device__ __forceinline__ int plane_target_dyn(int p, const FrontierBufs& B, co
 // Requests (and, with edit, edits) the targets of the violating planes m of anchor a.  Whole
 // waves call it; lanes without an anchor pass m = 0.  One plane per lane per round.
 template <int D>
-__device__ __forceinline__ void anchor_requests(const FrontierBufs& B, const Dims& dm, int a, uint32_t m, int it,
-                                                bool edit, int* cnt, int* changed_cnt) {
+__device__ __forceinline__ void anchor_requests(const FrontierView& B, const Dims& dm, int a, uint32_t m, int it,
+                                                bool edit, int* cnt, int* rc) {
     const float* gcur = B.gb[it & 1];
     for (;;) {
         if (__ballot(m != 0) == 0) break;
@@ -260,53 +369,168 @@ __device__ __forceinline__ void anchor_requests(const FrontierBufs& B, const Dim
             m &= m - 1u;
             target = plane_target_dyn<D, 0>(p, B, dm, a, gcur, cnt);
         }
-        request_apply<D>(B, dm, target, it, edit, changed_cnt);
+        request_apply<D>(B, dm, target, it, edit, rc);
     }
 }
 
 // ---- phases ------------------------------------------------------------------------------
 
 // Gradient of g^(it) for the dirty vertices (every vertex at iteration 0); brings the write
-// buffer up to date on them; clears the branch scan results and the next slot.
+// buffer up to date on them; lists the cells of f's branches that contain a dirty vertex (the
+// only branch cells whose pairing can have changed); clears the next slot.
 template <int D>
-__device__ __forceinline__ void phase_grad(const FrontierBufs& B, const Dims& dm, int it, int gtid, int gsize) {
+__device__ __forceinline__ void phase_grad(const FrontierView& B, const Dims& dm, int it, int gtid, int gsize) {
     if (gtid == 0) {
         Slot& s = slot_of(B, it + 1);
         for (int k = 0; k < CNT_WORDS; k++) s.cnt[k] = 0;
-        s.n_req = s.n_dv = s.n_da = s.n_vl = 0;
+        s.n_dv = s.n_da = s.n_vl = s.n_tc = s.n_db = s.n_scan = 0;
     }
-    for (int b = gtid; b < B.n_desc; b += gsize) B.dfirst[b] = INF32;
-    for (int b = gtid; b < B.n_asc; b += gsize) B.afirst[b] = INF32;
     const float* gcur = B.gb[it & 1];
     float* gnext = B.gb[(it + 1) & 1];
     if (it == 0) {
         for (int i = gtid; i < dm.n; i += gsize) grad_vertex<D>(i, gcur, B.gpl, dm);
         return;
     }
-    const int n = ld_relaxed(&slot_of(B, it).n_dv);
+    Slot& S = slot_of(B, it);
+    const int n = ld_relaxed(&S.n_dv);
     const int* list = B.dvl[it & 1];
-    for (int i = gtid; i < n; i += gsize) {
+    for (int base = 0; base < n; base += gsize) {
+        if (wave_done(base, gtid, n)) break;
+        const int i = base + gtid;
+        if (i >= n) continue;
         const int t = list[i];
         grad_vertex<D>(t, gcur, B.gpl, dm);
         gnext[t] = gcur[t];
     }
+    // the branch cells on the dirty vertices (each dirty vertex is listed once per iteration, so
+    // each cell appears at most D + 1 times)
+    if (B.vstart) {
+        for (int base = 0; base < n; base += gsize) {
+            if (wave_done(base, gtid, n)) break;
+            const int i0 = base + gtid;
+            int e0 = 0, e1 = 0;
+            if (i0 < n) {
+                const int t = list[i0];
+                e0 = B.vstart[t];
+                e1 = B.vstart[t + 1];
+            }
+            int pos = wave_append_n(e1 - e0, &S.n_tc);
+            for (int e = e0; e < e1; e++) B.tcl[pos++] = B.ecell[e];
+        }
+    }
+}
+
+// First cell of f-branch k's cell range whose g pairing differs from f's, or INF32.
+template <int D>
+__device__ __forceinline__ bool branch_cell_differs(const FrontierView& B, const Dims& dm, bool asc, long long k) {
+    constexpr auto& g = G<D>::g;
+    if (!asc) {
+        const int v = B.dcell[k];
+        return B.fpl[v] != B.gpl[v];
+    }
+    const int T = B.acell[k];
+    const int a = T / g.ntypes[D];
+    const int tp = T - a * g.ntypes[D] + g.base[D];
+    const size_t o = (size_t)tp * dm.n + a;
+    return B.fpl[o] != B.gpl[o];
+}
+
+// Keeping first[] (each f-branch's first cell whose g pairing differs) current, in two passes
+// separated by a synchronisation.  Before iteration it, no cell of branch b before first[b]
+// differed, and only the touched cells can have changed since.
+// Pass A (touched_cells): each touched cell marks its branch and, if it differs now, lowers
+// newmin[branch] to it.
+template <int D>
+__device__ __forceinline__ void touched_cells(const FrontierView& B, const Dims& dm, int it, int gtid, int gsize) {
+    Slot& S = slot_of(B, it);
+    const int n = ld_relaxed(&S.n_tc);
+    const unsigned stamp = (unsigned)it + 1u;
+    for (int base = 0; base < n; base += gsize) {
+        if (wave_done(base, gtid, n)) break;
+        const int i0 = base + gtid;
+        bool mine = false;
+        int bb = 0;
+        if (i0 < n) {
+            const int kk = B.tcl[i0];
+            const bool asc = kk >= B.n_dcell;
+            const int k = asc ? kk - (int)B.n_dcell : kk;
+            bb = asc ? B.n_desc + B.acbr[k] : B.dcbr[k];
+            mine = atomicMax(&B.bstamp[bb], stamp) < stamp;
+            if (branch_cell_differs<D>(B, dm, asc, k)) atomicMin(&B.newmin[bb], k);
+        }
+        const int idx = wave_append(mine, &S.n_db);
+        if (mine) B.dbl[idx] = bb;
+    }
+}
+
+// Pass B (phase_bscan): for each marked branch, if its old first cell still differs the new
+// first is the smaller of it and newmin; otherwise the first differing cell after the old first
+// (searched only up to newmin), else newmin.  One wave per branch, 64 cells per step.
+template <int D>
+__device__ __forceinline__ void phase_bscan(const FrontierView& B, const Dims& dm, int it, int gtid, int gsize) {
+    if (it == 0 || B.tier < 3) return;
+    Slot& S = slot_of(B, it);
+    const int n = ld_relaxed(&S.n_db);
+    const int lane = __lane_id();
+    int scanned = 0;
+    for (int i = gtid >> 6; i < n; i += gsize >> 6) {
+        const int bb = B.dbl[i];
+        const bool asc = bb >= B.n_desc;
+        const int b = asc ? bb - B.n_desc : bb;
+        int* first = asc ? B.afirst : B.dfirst;
+        const int64_t* off = asc ? B.aoff : B.doff;
+        const int old = first[b];
+        const int nm = B.newmin[bb];
+        int res;
+        if (old != INF32 && branch_cell_differs<D>(B, dm, asc, old)) {
+            res = old < nm ? old : nm;
+        } else {
+            res = nm;
+            const long long hi = off[b + 1];
+            const long long end = nm < hi ? nm : hi;
+            long long k0 = old == INF32 ? end : (long long)old + 1;
+            for (; k0 < end; k0 += 64) {
+                const long long k = k0 + lane;
+                const bool d = k < end && branch_cell_differs<D>(B, dm, asc, k);
+                const unsigned long long m = __ballot(d);
+                scanned += 64;
+                if (m) {
+                    res = (int)(k0 + __ffsll((long long)m) - 1);
+                    break;
+                }
+            }
+        }
+        if (lane == 0) {
+            first[b] = res;
+            B.newmin[bb] = INF32;
+        }
+    }
+    if (lane == 0 && scanned) atomicAdd(&S.n_scan, scanned);
 }
 
 // Violation masks of the affected anchors (every anchor at iteration 0), the targets of every
 // violating anchor (edited at once when edit is set), the violation list of the next iteration,
 // and the speculative first-difference scan along f's branches.
 template <int D>
-__device__ __forceinline__ void phase_vr(const FrontierBufs& B, const Dims& dm, int it, bool edit, int gtid,
+__device__ __forceinline__ void phase_vr(const FrontierView& B, const Dims& dm, int it, bool edit, int gtid,
                                          int gsize) {
     Slot& S = slot_of(B, it);
     int* n_next = &slot_of(B, it + 1).n_vl;
     int* next = B.vl[(it + 1) & 1];
     int cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    int changed = 0;
-    // affected anchors: new masks
+    int rc[2] = {0, 0};
+    // One index space: the affected anchors (every anchor at iteration 0) get new masks; the
+    // anchors listed by the previous iteration and not affected since keep theirs.
     const int na = it == 0 ? dm.n : ld_relaxed(&S.n_da);
+    const int nl = it == 0 ? 0 : ld_relaxed(&S.n_vl);
+    const int ntot = na + nl;
     const int* alist = B.dal[it & 1];
-    for (int i0 = gtid; i0 - (int)threadIdx.x < na; i0 += gsize) {
+    const int* vlist = B.vl[it & 1];
+    const unsigned astamp_it = (unsigned)it;
+    const unsigned* astamp = B.astamp[it & 1];
+    for (int base = 0; base < ntot; base += gsize) {
+        if (wave_done(base, gtid, ntot)) break;
+        const int i0 = base + gtid;
         uint32_t m = 0;
         int a = 0;
         if (i0 < na) {
@@ -315,56 +539,43 @@ __device__ __forceinline__ void phase_vr(const FrontierBufs& B, const Dims& dm, 
             coords(dm, a, x, y, z);
             vmask_plane<D, 0>(dm, a, x, y, z, B.fpl, B.gpl, B.tier, m);
             B.vmask[a] = m;
-        }
-        const int idx = wave_append(m != 0, n_next);
-        if (m != 0) next[idx] = a;
-        anchor_requests<D>(B, dm, a, m, it, edit, cnt, &changed);
-    }
-    // anchors listed from the previous iteration and not affected since: unchanged masks
-    const int nl = ld_relaxed(&S.n_vl);
-    const int* vlist = B.vl[it & 1];
-    const unsigned astamp_it = (unsigned)it;
-    const unsigned* astamp = B.astamp[it & 1];
-    for (int i0 = gtid; i0 - (int)threadIdx.x < nl; i0 += gsize) {
-        uint32_t m = 0;
-        int a = 0;
-        if (i0 < nl) {
-            a = vlist[i0];
+        } else if (i0 < ntot) {
+            a = vlist[i0 - na];
             if (astamp[a] != astamp_it) m = B.vmask[a];
         }
         const int idx = wave_append(m != 0, n_next);
         if (m != 0) next[idx] = a;
-        anchor_requests<D>(B, dm, a, m, it, edit, cnt, &changed);
+        anchor_requests<D>(B, dm, a, m, it, edit, cnt, rc);
     }
-    // speculative separatrix scan: first cell of each f-branch whose g pairing differs
+    // first differing cell of the f-branches, kept up to date for the separatrix step: every
+    // branch at iteration 0 (first[] starts at INF32), afterwards the branches listed by the
+    // gradient pass
     if (B.tier >= 3) {
-        constexpr auto& g = G<D>::g;
-        for (long long k = gtid; k < B.n_dcell; k += gsize) {
-            const int v = B.dcell[k];
-            if (B.fpl[v] != B.gpl[v]) atomicMin(&B.dfirst[B.dcbr[k]], (int)k);
-        }
-        for (long long k = gtid; k < B.n_acell; k += gsize) {
-            const int T = B.acell[k];
-            const int a = T / g.ntypes[D];
-            const int tp = T - a * g.ntypes[D] + g.base[D];
-            const size_t o = (size_t)tp * dm.n + a;
-            if (B.fpl[o] != B.gpl[o]) atomicMin(&B.afirst[B.acbr[k]], (int)k);
+        if (it == 0) {
+            for (long long k = gtid; k < B.n_dcell; k += gsize)
+                if (branch_cell_differs<D>(B, dm, false, k)) atomicMin(&B.dfirst[B.dcbr[k]], (int)k);
+            for (long long k = gtid; k < B.n_acell; k += gsize)
+                if (branch_cell_differs<D>(B, dm, true, k)) atomicMin(&B.afirst[B.acbr[k]], (int)k);
+        } else {
+            touched_cells<D>(B, dm, it, gtid, gsize);
         }
     }
     block_add_counters<8>(S.cnt + CNT_FP0, cnt);
-    block_add_counters<1>(S.cnt + CNT_CHANGED, &changed);
+    block_add_counters<2>(S.cnt + CNT_NREQ, rc);
 }
 
 // Troublemaker targets (apex of the f-pair of each branch's first differing cell), edited at
 // once.  Only called when iteration it has no critical-cell violation.
 template <int D>
-__device__ __forceinline__ void phase_sapply(const FrontierBufs& B, const Dims& dm, int it, bool edit, int gtid,
+__device__ __forceinline__ void phase_sapply(const FrontierView& B, const Dims& dm, int it, bool edit, int gtid,
                                              int gsize) {
     constexpr auto& g = G<D>::g;
     int c[2] = {0, 0};
-    int changed = 0;
+    int rc[2] = {0, 0};
     const int nb = B.n_desc + B.n_asc;
-    for (int i0 = gtid; i0 - (int)threadIdx.x < nb; i0 += gsize) {
+    for (int base = 0; base < nb; base += gsize) {
+        if (wave_done(base, gtid, nb)) break;
+        const int i0 = base + gtid;
         int target = -1;
         if (i0 < nb) {
             const bool asc = i0 >= B.n_desc;
@@ -413,17 +624,17 @@ __device__ __forceinline__ void phase_sapply(const FrontierBufs& B, const Dims& 
                 }
             }
         }
-        request_apply<D>(B, dm, target, it, edit, &changed);
+        request_apply<D>(B, dm, target, it, edit, rc);
     }
     block_add_counters<2>(slot_of(B, it).cnt + CNT_TM_DESC, c);
-    block_add_counters<1>(slot_of(B, it).cnt + CNT_CHANGED, &changed);
+    block_add_counters<2>(slot_of(B, it).cnt + CNT_NREQ, rc);
 }
 
 // ---- iteration bookkeeping ----------------------------------------------------------------
 
 // End state of iteration it from its counters (all threads agree): 0 go on, 1 converged,
 // 2 iteration cap, 3 stalled.  The cap is tested before the stall, as no edit is made at the cap.
-__device__ __forceinline__ int iteration_state(const FrontierBufs& B, int it) {
+__device__ __forceinline__ int iteration_state(const FrontierView& B, int it) {
     const unsigned long long viol = violations(B, it);
     if (viol == 0) return 1;
     if ((long long)it == B.max_iters) return 2;
@@ -432,7 +643,7 @@ __device__ __forceinline__ int iteration_state(const FrontierBufs& B, int it) {
 }
 
 // Log record, step counters and residual of iteration it (one thread).
-__device__ __forceinline__ void record_iteration(const FrontierBufs& B, int it, int state) {
+__device__ __forceinline__ void record_iteration(const FrontierView& B, int it, int state) {
     Ctl* c = B.ctl;
     const Slot& S = slot_of(B, it);
     if (state == 2 || state == 3) c->residual = (long long)violations(B, it);
@@ -442,9 +653,15 @@ __device__ __forceinline__ void record_iteration(const FrontierBufs& B, int it, 
         long long* rec = B.log + (size_t)it * DMT_LOG_WORDS;
         rec[0] = cstep ? 1 : 2;
         for (int k = 1; k < CNT_NREQ; k++) rec[k] = (long long)ld_relaxed(&S.cnt[k]);
-        rec[CNT_NREQ] = ld_relaxed(&S.n_req);
+        rec[CNT_NREQ] = (long long)ld_relaxed(&S.cnt[CNT_NREQ]);
         rec[CNT_CHANGED] = (long long)ld_relaxed(&S.cnt[CNT_CHANGED]);
-        for (int k = CNT_CHANGED + 1; k < DMT_LOG_WORDS; k++) rec[k] = 0;
+        rec[13] = it == 0 ? 0 : ld_relaxed(&S.n_dv);
+        rec[14] = it == 0 ? 0 : ld_relaxed(&S.n_da);
+        rec[15] = it == 0 ? 0 : ld_relaxed(&S.n_vl);
+        rec[16] = ld_relaxed(&S.n_db);
+        rec[17] = ld_relaxed(&S.n_scan);
+        rec[18] = it == 0 ? 0 : ld_relaxed(&S.n_tc);
+        for (int k = 19; k < DMT_LOG_WORDS; k++) rec[k] = 0;
     }
     if (cstep) c->c_it++; else c->s_it++;
 }
@@ -454,153 +671,136 @@ __global__ void k_fr_init(Ctl* c) {
     c->done = 0;
     c->c_it = c->s_it = 0;
     c->residual = 0;
+    c->ph[0] = c->ph[1] = c->ph[2] = 0;
     for (int i = 0; i < 3; i++) {
         for (int k = 0; k < CNT_WORDS; k++) c->slot[i].cnt[k] = 0;
-        c->slot[i].n_req = c->slot[i].n_dv = c->slot[i].n_da = c->slot[i].n_vl = 0;
+        c->slot[i].n_dv = c->slot[i].n_da = c->slot[i].n_vl = c->slot[i].n_db = 0;
+        c->slot[i].n_scan = c->slot[i].n_tc = 0;
     }
 }
 
-// ---- persistent form: the loops of a batch of jobs in one cooperative launch ----------------
+// ---- workgroup-resident form: each job's loop runs inside one workgroup ---------------------
 
-// Loop state of one job in the persistent kernel, indexed by pass parity: pass p reads [p & 1]
-// (written by the previous pass's decision, several barriers earlier) and the decision of pass
-// p writes [(p + 1) & 1], so the single writer never races with readers.
-struct JobRun {
-    int itp[2];             // iteration the job is at
-    int donep[2];           // end state (0 = running)
-    int log_cap;            // records the job's log can hold (ignored when it has no log)
-    int ndim;               // 2 or 3
-};
-
-struct BatchCtl {
-    unsigned bar_count, bar_gen;  // grid barrier
-    int err;                      // 1: a grid barrier timed out
-    int parity;                   // pass parity to resume from
-    unsigned long long ph[4];     // wall-clock ticks (100 MHz) per phase, seen from block 0
-};
-
-__device__ __forceinline__ bool batch_barrier(BatchCtl* c, unsigned nblocks, unsigned& gen,
-                                              unsigned long long timeout) {
-    __shared__ int ok_sh;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int ok = 1;
-        const unsigned arrived = __hip_atomic_fetch_add(&c->bar_count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        if (arrived == nblocks - 1) {
-            __hip_atomic_store(&c->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(&c->bar_gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            const unsigned long long t0 = wall_clock64();
-            while (__hip_atomic_load(&c->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-                __builtin_amdgcn_s_sleep(2);
-                if (wall_clock64() - t0 > timeout) { ok = 0; break; }
-            }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        if (!ok || __hip_atomic_load(&c->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-            ok = 0;
-            __hip_atomic_store(&c->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        ok_sh = ok;
-    }
-    __syncthreads();
-    gen++;
-    return ok_sh != 0;
-}
-
-// The frontier loops of n_jobs fields (2D and 3D mixed), advanced in lockstep: one pass runs
-// one iteration of every unfinished job, so each grid barrier is shared by all of them.
-// Precondition: the gradient and violation passes of each job's current iteration are done
-// (iteration 0's run as full-grid launches before the first launch of this kernel).
-// Per pass: troublemaker passes [barrier], decisions, gradient passes, barrier, violation
-// passes, barrier.  Pauses (and can be launched again) when a job's log is full or after
-// max_passes passes, so every launch ends.
-__global__ void __launch_bounds__(256) k_fr_loop_batch(const FrontierBufs* __restrict__ jobs,
-                                                       const Dims* __restrict__ dims, JobRun* __restrict__ run,
-                                                       int n_jobs, BatchCtl* bc, unsigned long long timeout,
-                                                       int max_passes) {
-    const unsigned nblocks = gridDim.x;
-    const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
-    const int gsize = gridDim.x * blockDim.x;
-    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
-    unsigned gen = __hip_atomic_load(&bc->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    int p = __hip_atomic_load(&bc->parity, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (!batch_barrier(bc, nblocks, gen, timeout)) return;   // every block starts from one generation
+// The loop of one job from the end of its iteration ctl->it's violation pass (the
+// precondition: that iteration's gradient and violation passes are done), in one workgroup,
+// synchronised by workgroup barriers only.  Returns when the job ends, when its log is full
+// or after max_passes iterations; the host launches it again in the last two cases.
+template <int D>
+__device__ __forceinline__ void run_job_wg(const FrontierView& B, int max_passes) {
+    const Dims dm = B.dm;
+    Ctl* c = B.ctl;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    if (ld_relaxed(&c->done)) return;
+    int it = ld_relaxed(&c->it);
     unsigned long long ph[3] = {0, 0, 0};
-    unsigned long long t = lead ? wall_clock64() : 0;
+    unsigned long long t = tid == 0 ? wall_clock64() : 0;
+    unsigned long long t_it = t;   // start of the current iteration's gradient pass
     auto tick = [&](int k) {
-        if (lead) { const unsigned long long t1 = wall_clock64(); ph[k] += t1 - t; t = t1; }
+        if (tid == 0) { const unsigned long long t1 = wall_clock64(); ph[k] += t1 - t; t = t1; }
     };
+    // decisions are taken by wave 0 and shared through LDS; each variable is written again only
+    // after several more workgroup barriers, when every wave has read it
+    __shared__ int sstep_sh, state_sh;
     for (int pass = 0; pass < max_passes; pass++) {
-        const int q = p & 1;
-        bool any = false, pause = false;
-        for (int j = 0; j < n_jobs; j++) {
-            if (ld_relaxed(&run[j].donep[q])) continue;
-            any = true;
-            if (jobs[j].log && ld_relaxed(&run[j].itp[q]) >= run[j].log_cap) pause = true;
+        if (B.log && it >= B.log_cap) break;
+        if (tid < 64) {
+            const bool s_step = B.tier >= 3 && c_total(slot_of(B, it)) == 0;
+            if (tid == 0) sstep_sh = s_step;
         }
-        if (!any || pause) break;
-        // troublemaker passes of the jobs without critical-cell violations
-        bool any_s = false;
-        for (int j = 0; j < n_jobs; j++) {
-            if (ld_relaxed(&run[j].donep[q])) continue;
-            const FrontierBufs& B = jobs[j];
-            const int it = ld_relaxed(&run[j].itp[q]);
-            if (B.tier < 3 || c_total(slot_of(B, it)) != 0) continue;
-            any_s = true;
-            const bool edit = (long long)it != B.max_iters;
-            if (run[j].ndim == 2) phase_sapply<2>(B, dims[j], it, edit, gtid, gsize);
-            else phase_sapply<3>(B, dims[j], it, edit, gtid, gsize);
+        __syncthreads();
+        if (sstep_sh) {
+            phase_sapply<D>(B, dm, it, (long long)it != B.max_iters, tid, nt);
+            __syncthreads();
         }
-        if (any_s) {
-            if (!batch_barrier(bc, nblocks, gen, timeout)) return;
-            tick(0);
-        }
-        // decisions (every thread reaches the same ones) and the next iteration's gradient pass;
-        // a finished job's state is carried to the other parity too, or the next pass would
-        // read the stale entry and take the job up again
-        for (int j = 0; j < n_jobs; j++) {
-            const int dq = ld_relaxed(&run[j].donep[q]);
-            if (dq) {
-                if (lead) {
-                    run[j].itp[q ^ 1] = ld_relaxed(&run[j].itp[q]);
-                    run[j].donep[q ^ 1] = dq;
-                }
-                continue;
-            }
-            const FrontierBufs& B = jobs[j];
-            const int it = ld_relaxed(&run[j].itp[q]);
+        if (tid < 64) {
             const int st = iteration_state(B, it);
-            if (lead) {
+            if (tid == 0) {
                 record_iteration(B, it, st);
-                run[j].itp[q ^ 1] = st ? it : it + 1;
-                run[j].donep[q ^ 1] = st;
-                B.ctl->it = st ? it : it + 1;
-                B.ctl->done = st;
+                if (B.log && st == 0) B.log[(size_t)it * DMT_LOG_WORDS + 19] = (long long)(wall_clock64() - t_it);
+                c->it = st ? it : it + 1;
+                c->done = st;
+                state_sh = st;
             }
-            if (st) continue;
-            if (run[j].ndim == 2) phase_grad<2>(B, dims[j], it + 1, gtid, gsize);
-            else phase_grad<3>(B, dims[j], it + 1, gtid, gsize);
         }
-        if (!batch_barrier(bc, nblocks, gen, timeout)) return;
+        __syncthreads();
+        const int st = state_sh;
+        tick(0);
+        if (st) break;
+        it++;
+        if (tid == 0) t_it = wall_clock64();
+        phase_grad<D>(B, dm, it, tid, nt);
+        __syncthreads();
         tick(1);
-        for (int j = 0; j < n_jobs; j++) {
-            if (ld_relaxed(&run[j].donep[q])) continue;
-            const FrontierBufs& B = jobs[j];
-            const int it = ld_relaxed(&run[j].itp[q]);
-            if (iteration_state(B, it)) continue;
-            const bool edit = (long long)(it + 1) != B.max_iters;
-            if (run[j].ndim == 2) phase_vr<2>(B, dims[j], it + 1, edit, gtid, gsize);
-            else phase_vr<3>(B, dims[j], it + 1, edit, gtid, gsize);
+        phase_vr<D>(B, dm, it, (long long)it != B.max_iters, tid, nt);
+        __syncthreads();
+        if (B.tier >= 3) {
+            phase_bscan<D>(B, dm, it, tid, nt);
+            __syncthreads();
         }
-        if (!batch_barrier(bc, nblocks, gen, timeout)) return;
         tick(2);
-        p++;
     }
-    if (lead) {
-        for (int k = 0; k < 3; k++) bc->ph[k] += ph[k];
-        bc->parity = p;
+    if (tid == 0)
+        for (int k = 0; k < 3; k++) c->ph[k] += ph[k];
+    __syncthreads();
+}
+
+// Workgroup size of the resident loop: the 3D passes need twice the registers of the 2D ones.
+template <int D>
+struct WgThreads {
+    static constexpr int value = D == 2 ? 1024 : 512;
+};
+
+// Workgroups take jobs (all of dimension D) from a queue (an atomic counter starting at 0)
+// until none is left.
+template <int D>
+__global__ void __launch_bounds__(WgThreads<D>::value) k_fr_loop_wg(const FrontierBufs* __restrict__ jobs,
+                                                                    int n_jobs, int* queue, int max_passes) {
+    __shared__ int job_sh;
+    for (;;) {
+        if (threadIdx.x == 0) job_sh = atomicAdd(queue, 1);
+        __syncthreads();
+        const int j = __builtin_amdgcn_readfirstlane(job_sh);   // uniform: job fields load as scalars
+        __syncthreads();
+        if (j >= n_jobs) return;
+        run_job_wg<D>(view(jobs[j]), max_passes);
     }
+}
+
+// Vertex -> branch cells of f: one entry per (vertex, cell) of every branch cell (descending
+// cells are vertices; an ascending top cell contributes each of its D + 1 vertices).  Pass 0
+// counts entries per vertex into pos; pass 1 (pos = exclusive offsets) fills ecell.  The order
+// of entries within a vertex depends on scheduling; their use (marking branches) does not.
+template <int D>
+__global__ void __launch_bounds__(256) k_fr_branch_map(FrontierBufs hb, int pass, int* __restrict__ pos,
+                                                       int* __restrict__ ecell) {
+    const FrontierView& B = view(hb);
+    constexpr auto& g = G<D>::g;
+    const Dims dm = B.dm;
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long ne = B.n_dcell + (long long)(D + 1) * B.n_acell;
+    if (e >= ne) return;
+    int v, kk;
+    if (e < B.n_dcell) {
+        v = B.dcell[e];
+        kk = (int)e;
+    } else {
+        const long long k = (e - B.n_dcell) / (D + 1);
+        const int j = (int)(e - B.n_dcell - k * (D + 1));
+        const int T = B.acell[k];
+        const int a = T / g.ntypes[D];
+        const int tp = T - a * g.ntypes[D] + g.base[D];
+        v = a;
+#pragma unroll
+        for (int q = g.base[D]; q < g.base[D] + g.ntypes[D]; q++) {
+            if (q != tp) continue;
+#pragma unroll
+            for (int r = 0; r <= D; r++)
+                if (r == j) v = a + g.bvert[q][r][0] + dm.nx * g.bvert[q][r][1] + dm.nxy * g.bvert[q][r][2];
+        }
+        kk = (int)(B.n_dcell + k);
+    }
+    if (pass == 0) atomicAdd(&pos[v], 1);
+    else ecell[atomicAdd(&pos[v], 1)] = kk;
 }
 
 // ---- launch-per-phase form (when a cooperative launch is not available) --------------------
@@ -608,13 +808,15 @@ __global__ void __launch_bounds__(256) k_fr_loop_batch(const FrontierBufs* __res
 __device__ __forceinline__ bool running(const Ctl* c) { return ld_relaxed(&c->done) == 0; }
 
 template <int D>
-__global__ void __launch_bounds__(256) k_fr_grad(FrontierBufs B, Dims dm) {
+__global__ void __launch_bounds__(256) k_fr_grad(FrontierBufs hb, Dims dm) {
+    const FrontierView& B = view(hb);
     if (!running(B.ctl)) return;
     phase_grad<D>(B, dm, ld_relaxed(&B.ctl->it), blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
 }
 
 template <int D>
-__global__ void __launch_bounds__(256) k_fr_vr(FrontierBufs B, Dims dm) {
+__global__ void __launch_bounds__(256) k_fr_vr(FrontierBufs hb, Dims dm) {
+    const FrontierView& B = view(hb);
     if (!running(B.ctl)) return;
     const int it = ld_relaxed(&B.ctl->it);
     phase_vr<D>(B, dm, it, (long long)it != B.max_iters, blockIdx.x * blockDim.x + threadIdx.x,
@@ -622,14 +824,23 @@ __global__ void __launch_bounds__(256) k_fr_vr(FrontierBufs B, Dims dm) {
 }
 
 template <int D>
-__global__ void __launch_bounds__(256) k_fr_sapply(FrontierBufs B, Dims dm) {
+__global__ void __launch_bounds__(256) k_fr_bscan(FrontierBufs hb, Dims dm) {
+    const FrontierView& B = view(hb);
+    if (!running(B.ctl)) return;
+    phase_bscan<D>(B, dm, ld_relaxed(&B.ctl->it), blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+}
+
+template <int D>
+__global__ void __launch_bounds__(256) k_fr_sapply(FrontierBufs hb, Dims dm) {
+    const FrontierView& B = view(hb);
     const int it = ld_relaxed(&B.ctl->it);
     if (!running(B.ctl) || B.tier < 3 || c_total(slot_of(B, it)) != 0) return;
     phase_sapply<D>(B, dm, it, (long long)it != B.max_iters, blockIdx.x * blockDim.x + threadIdx.x,
                     gridDim.x * blockDim.x);
 }
 
-__global__ void k_fr_finish(FrontierBufs B) {
+__global__ void k_fr_finish(FrontierBufs hb) {
+    const FrontierView& B = view(hb);
     Ctl* c = B.ctl;
     if (c->done) return;
     const int it = c->it;

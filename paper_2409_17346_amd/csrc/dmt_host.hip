@@ -4,6 +4,7 @@
 // sequences launches, sizes buffers and reads counters.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cfloat>
 #include <cmath>
 #include <cstdio>
@@ -44,11 +45,14 @@ struct MscBufs {
 
 // Device state of one correction job.
 struct JobWs {
-    DevBuf lo, g0, g1, state, fpl, gpl, vmask, vl0, vl1, dvl0, dvl1, dal0, dal1, vstamp, astamp, astamp1, rstamp, ctl;
+    DevBuf lo, g0, g1, state, fpl, gpl, vmask, vl0, vl1, dvl0, dvl1, dal0, dal1, vstamp, astamp, astamp1, rstamp;
+    DevBuf vpos, vstart, tsum, toff, ecell, bstamp, tcl, dbl, newmin;
     MscBufs msc;
     std::vector<DevBuf*> all() {
-        std::vector<DevBuf*> v = {&lo, &g0, &g1, &state, &fpl, &gpl, &vmask, &vl0, &vl1, &dvl0, &dvl1, &dal0, &dal1,
-                                  &vstamp, &astamp, &astamp1, &rstamp, &ctl};
+        std::vector<DevBuf*> v = {&lo,     &g0,     &g1,      &state,  &fpl,   &gpl,   &vmask,  &vl0,
+                                  &vl1,    &dvl0,   &dvl1,    &dal0,   &dal1,  &vstamp, &astamp, &astamp1,
+                                  &rstamp, &vpos,   &vstart,  &tsum,   &toff,   &ecell, &bstamp, &tcl,
+                                  &dbl,    &newmin};
         for (DevBuf* b : msc.all()) v.push_back(b);
         return v;
     }
@@ -61,13 +65,13 @@ struct dmt_context {
     std::string err;
     std::vector<JobWs> ws;                 // one workspace per job of the last batch (ws[0]: single calls)
     MscBufs msc;                           // results of dmt_extract_msc
-    DevBuf gpl, req, cnt, flags, part, blk, blkoff, ll_idx, ll_val, dlog, jobs_dev, dims_dev, run_dev, bctl;
+    DevBuf gpl, req, cnt, flags, part, blk, blkoff, ll_idx, ll_val, dlog, jobs_dev, ctl_all, queue;
     int64_t n_lossless = 0;
     std::vector<int64_t> log;
     unsigned long long* hcnt = nullptr;    // pinned
     int64_t* hscratch = nullptr;           // pinned
-    BatchCtl* hbctl = nullptr;             // pinned
     std::vector<Ctl> hctl;                 // per-job control blocks read back after the loop
+    unsigned long long ph[3] = {0, 0, 0};  // loop phase ticks of the last correction call
     // kernel timing: event pairs per kernel family, recorded on the launch stream
     bool prof = false;
     std::vector<hipEvent_t> ev_pool;
@@ -360,7 +364,7 @@ dmt_status job_setup(dmt_context* c, Job& J, unsigned* flag, hipStream_t st) {
 
 // a2 (f-branches), frontier buffers and control block of a job whose setup passed; fills J.B.
 template <int D>
-dmt_status job_frontier(dmt_context* c, Job& J, hipStream_t st) {
+dmt_status job_frontier(dmt_context* c, Job& J, Ctl* ctl, hipStream_t st) {
     JobWs& w = *J.w;
     const int n = J.dm.n;
     w.msc.valid = false;
@@ -368,7 +372,6 @@ dmt_status job_frontier(dmt_context* c, Job& J, hipStream_t st) {
         ProfScope ps(c, DMT_PROF_MSC, st, n);
         TRY(build_msc<D>(c, w.msc, P<uint8_t>(w.fpl), J.dm, false, st));
     }
-    ENSURE(c, w.ctl, sizeof(Ctl));
     ENSURE(c, w.g1, sizeof(float) * n);
     ENSURE(c, w.vmask, sizeof(uint32_t) * n);
     ENSURE(c, w.vl0, sizeof(int) * n);
@@ -386,12 +389,14 @@ dmt_status job_frontier(dmt_context* c, Job& J, hipStream_t st) {
     HIPCHK(c, hipMemsetAsync(w.astamp.p, 0, sizeof(unsigned) * n, st));
     HIPCHK(c, hipMemsetAsync(w.astamp1.p, 0, sizeof(unsigned) * n, st));
     HIPCHK(c, hipMemsetAsync(w.rstamp.p, 0, sizeof(unsigned) * n, st));
-    k_fr_init<<<1, 1, 0, st>>>(P<Ctl>(w.ctl));
+    k_fr_init<<<1, 1, 0, st>>>(ctl);
     CHECK_LAUNCH(c);
 
     FrontierBufs& B = J.B;
     B = FrontierBufs{};
-    B.ctl = P<Ctl>(w.ctl);
+    B.ctl = ctl;
+    B.dm = J.dm;
+    B.ndim = D;
     B.f = J.f;
     B.gh = J.gh;
     B.lo = P<float>(w.lo);
@@ -420,6 +425,46 @@ dmt_status job_frontier(dmt_context* c, Job& J, hipStream_t st) {
         B.dfirst = P<int>(m.dfirst); B.afirst = P<int>(m.afirst);
         B.n_dcell = m.n_desc_cells; B.n_acell = m.n_asc_cells;
         B.n_desc = (int)m.n_desc; B.n_asc = (int)m.n_asc;
+        // first[] starts at "no difference" (iteration 0 scans every branch); the vertex ->
+        // branch lists let later iterations rescan only the branches near their edits
+        TRY(fill_i32(c, B.dfirst, B.n_desc, INF32, st));
+        TRY(fill_i32(c, B.afirst, B.n_asc, INF32, st));
+        const int64_t nbr = m.n_desc + m.n_asc;
+        const int64_t ne = m.n_desc_cells + (int64_t)(D + 1) * m.n_asc_cells;
+        if (ne >= (int64_t)INT32_MAX) return fail(c, DMT_E_INVALID, "too many separatrix cells");
+        const int ntiles = (int)((n + 1023) / 1024);
+        ENSURE(c, w.vpos, sizeof(int) * n);
+        ENSURE(c, w.vstart, sizeof(int) * (n + 1));
+        ENSURE(c, w.tsum, sizeof(int) * ntiles);
+        ENSURE(c, w.toff, sizeof(int64_t) * (ntiles + 1));
+        ENSURE(c, w.ecell, sizeof(int) * (size_t)ne);
+        ENSURE(c, w.tcl, sizeof(int) * (size_t)ne);
+        ENSURE(c, w.bstamp, sizeof(unsigned) * (size_t)nbr);
+        ENSURE(c, w.dbl, sizeof(int) * (size_t)nbr);
+        ENSURE(c, w.newmin, sizeof(int) * (size_t)nbr);
+        TRY(fill_i32(c, P<int>(w.newmin), nbr, INF32, st));
+        HIPCHK(c, hipMemsetAsync(w.vpos.p, 0, sizeof(int) * n, st));
+        HIPCHK(c, hipMemsetAsync(w.bstamp.p, 0, sizeof(unsigned) * (size_t)nbr, st));
+        // counting sort of the entries by vertex: counts, offsets, fill
+        if (ne) {
+            k_fr_branch_map<D><<<nblocks(ne), TPB, 0, st>>>(B, 0, P<int>(w.vpos), P<int>(w.ecell));
+            CHECK_LAUNCH(c);
+        }
+        k_tile_sum<<<ntiles, TPB, 0, st>>>(P<int>(w.vpos), n, P<int>(w.tsum));
+        CHECK_LAUNCH(c);
+        TRY(scan(c, P<int>(w.tsum), ntiles, P<int64_t>(w.toff), nullptr, st));
+        k_tile_scan<<<ntiles, TPB, 0, st>>>(P<int>(w.vpos), n, P<int64_t>(w.toff), P<int>(w.vstart));
+        CHECK_LAUNCH(c);
+        if (ne) {
+            k_fr_branch_map<D><<<nblocks(ne), TPB, 0, st>>>(B, 1, P<int>(w.vpos), P<int>(w.ecell));
+            CHECK_LAUNCH(c);
+        }
+        B.vstart = P<int>(w.vstart);
+        B.ecell = P<int>(w.ecell);
+        B.bstamp = P<unsigned>(w.bstamp);
+        B.tcl = P<int>(w.tcl);
+        B.dbl = P<int>(w.dbl);
+        B.newmin = P<int>(w.newmin);
     }
     B.delta = ldexpf(J.xi, -J.o.q_max);
     B.q_max = J.o.q_max;
@@ -433,8 +478,12 @@ template <int D>
 dmt_status job_iteration0(dmt_context* c, Job& J, hipStream_t st) {
     const int n = J.dm.n;
     const unsigned gfull = nblocks(n) < 2048u ? nblocks(n) : 2048u;
-    ProfScope ps(c, DMT_PROF_GRADIENT, st, n);
-    k_fr_grad<D><<<gfull, TPB, 0, st>>>(J.B, J.dm);
+    {
+        ProfScope ps(c, DMT_PROF_GRADIENT, st, n);
+        k_fr_grad<D><<<gfull, TPB, 0, st>>>(J.B, J.dm);
+        CHECK_LAUNCH(c);
+    }
+    ProfScope ps(c, DMT_PROF_CLASSIFY, st, n);
     k_fr_vr<D><<<gfull, TPB, 0, st>>>(J.B, J.dm);
     CHECK_LAUNCH(c);
     return DMT_OK;
@@ -458,89 +507,85 @@ dmt_status grow_log(dmt_context* c, size_t need, int64_t keep, hipStream_t st) {
     return DMT_OK;
 }
 
-// The persistent loop over the jobs (one cooperative launch).  A single job may keep a log; the
-// kernel pauses when it is full and is launched again after the log has grown.
-dmt_status run_persistent(dmt_context* c, std::vector<Job*>& jobs, bool with_log, hipStream_t st) {
+// The loops of the jobs in workgroup-resident form: one launch per dimension present, one
+// workgroup per job at a time.  A single job may keep a log; its loop pauses when the log is
+// full and is launched again after the log has grown.  Every launch ends after a bounded
+// number of iterations.
+dmt_status run_wg(dmt_context* c, std::vector<Job*>& jobs, bool with_log, hipStream_t st) {
     const int nj = (int)jobs.size();
-    int ncu = 0, occ = 0, coop = 0;
-    HIPCHK(c, hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, c->device));
+    int ncu = 0, occ2 = 0, occ3 = 0;
     HIPCHK(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device));
-    HIPCHK(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(k_fr_loop_batch), TPB, 0));
-    if (!coop || occ < 1) return fail(c, DMT_E_HIP, "cooperative launch unavailable");
-    // The persistent grid only covers frontiers (iteration 0 runs as full-grid launches), and a
-    // grid barrier costs more the more blocks arrive at it, so the grid is small.
-    int want = 32;
-    if (const char* e = getenv("DMT_COOP_BLOCKS")) want = atoi(e) > 0 ? atoi(e) : want;
-    const int blocks = want < ncu * occ ? want : ncu * occ;
-
+    HIPCHK(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ2, reinterpret_cast<const void*>(k_fr_loop_wg<2>),
+                                                           WgThreads<2>::value, 0));
+    HIPCHK(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ3, reinterpret_cast<const void*>(k_fr_loop_wg<3>),
+                                                           WgThreads<3>::value, 0));
+    if (occ2 < 1 || occ3 < 1) return fail(c, DMT_E_HIP, "the loop kernel does not fit a compute unit");
+    // jobs ordered 2D first, then 3D; hb[k] belongs to jobs[order[k]] and to control block
+    // order[k] (control blocks follow the order of jobs)
+    std::vector<int> order;
+    for (int pass = 2; pass <= 3; pass++)
+        for (int j = 0; j < nj; j++)
+            if (jobs[j]->D == pass) order.push_back(j);
+    const int n2 = (int)std::count_if(jobs.begin(), jobs.end(), [](const Job* J) { return J->D == 2; });
     ENSURE(c, c->jobs_dev, sizeof(FrontierBufs) * nj);
-    ENSURE(c, c->dims_dev, sizeof(Dims) * nj);
-    ENSURE(c, c->run_dev, sizeof(JobRun) * nj);
-    ENSURE(c, c->bctl, sizeof(BatchCtl));
+    ENSURE(c, c->queue, sizeof(int) * 2);
     std::vector<FrontierBufs> hb(nj);
-    std::vector<Dims> hd(nj);
-    std::vector<JobRun> hr(nj);
     if (with_log) TRY(grow_log(c, 4096, 0, st));
     const int cap0 = with_log ? (int)(c->dlog.cap / (sizeof(long long) * DMT_LOG_WORDS)) : 0;
-    for (int j = 0; j < nj; j++) {
-        hb[j] = jobs[j]->B;
-        if (with_log) hb[j].log = P<long long>(c->dlog);
-        hd[j] = jobs[j]->dm;
-        hr[j] = JobRun{{0, 0}, {0, 0}, cap0, jobs[j]->D};
-    }
-    *c->hbctl = BatchCtl{};
-    HIPCHK(c, hipMemcpyAsync(c->jobs_dev.p, hb.data(), sizeof(FrontierBufs) * nj, hipMemcpyHostToDevice, st));
-    HIPCHK(c, hipMemcpyAsync(c->dims_dev.p, hd.data(), sizeof(Dims) * nj, hipMemcpyHostToDevice, st));
-    HIPCHK(c, hipMemcpyAsync(c->run_dev.p, hr.data(), sizeof(JobRun) * nj, hipMemcpyHostToDevice, st));
-    HIPCHK(c, hipMemcpyAsync(c->bctl.p, c->hbctl, sizeof(BatchCtl), hipMemcpyHostToDevice, st));
     // Every iteration that does not end a job edits at least one vertex, and a vertex takes at
     // most q_max + 1 edits (Section 4.6), so no job runs more than n (q_max + 1) + 1 iterations.
     int64_t bound = 0;
-    for (Job* J : jobs) {
+    for (int k = 0; k < nj; k++) {
+        const Job* J = jobs[order[k]];
+        hb[k] = J->B;
+        hb[k].log = with_log ? P<long long>(c->dlog) : nullptr;
+        hb[k].log_cap = cap0;
         const int64_t b = (int64_t)J->dm.n * (J->o.q_max + 1) + 1;
         bound = b > bound ? b : bound;
     }
-    const int max_passes = 1 << 16;
+    HIPCHK(c, hipMemcpyAsync(c->jobs_dev.p, hb.data(), sizeof(FrontierBufs) * nj, hipMemcpyHostToDevice, st));
+    const int max_passes = 1 << 18;
+    int64_t progress = -1;
     for (;;) {
-        const FrontierBufs* jp = P<FrontierBufs>(c->jobs_dev);
-        const Dims* dp = P<Dims>(c->dims_dev);
-        JobRun* rp = P<JobRun>(c->run_dev);
-        BatchCtl* bp = P<BatchCtl>(c->bctl);
-        int njobs = nj;
-        unsigned long long timeout = 500000000ull;   // 5 s of the 100 MHz wall clock
-        int mp = max_passes;
-        void* args[] = {&jp, &dp, &rp, &njobs, &bp, &timeout, &mp};
+        HIPCHK(c, hipMemsetAsync(c->queue.p, 0, sizeof(int) * 2, st));
         {
             ProfScope ps(c, DMT_PROF_LOOP, st, 0);
-            HIPCHK(c, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_fr_loop_batch), dim3(blocks),
-                                                 dim3(TPB), args, 0, st));
+            const FrontierBufs* jd = P<FrontierBufs>(c->jobs_dev);
+            if (n2) {
+                const int blocks = n2 < ncu * occ2 ? n2 : ncu * occ2;
+                k_fr_loop_wg<2><<<blocks, WgThreads<2>::value, 0, st>>>(jd, n2, P<int>(c->queue), max_passes);
+                CHECK_LAUNCH(c);
+            }
+            if (nj > n2) {
+                const int blocks = nj - n2 < ncu * occ3 ? nj - n2 : ncu * occ3;
+                k_fr_loop_wg<3><<<blocks, WgThreads<3>::value, 0, st>>>(jd + n2, nj - n2, P<int>(c->queue) + 1,
+                                                                         max_passes);
+                CHECK_LAUNCH(c);
+            }
         }
-        HIPCHK(c, hipMemcpyAsync(c->hbctl, c->bctl.p, sizeof(BatchCtl), hipMemcpyDeviceToHost, st));
-        HIPCHK(c, hipMemcpyAsync(hr.data(), c->run_dev.p, sizeof(JobRun) * nj, hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipMemcpyAsync(c->hctl.data(), c->ctl_all.p, sizeof(Ctl) * nj, hipMemcpyDeviceToHost, st));
         HIPCHK(c, hipStreamSynchronize(st));
-        if (c->hbctl->err) return fail(c, DMT_E_HIP, "grid barrier timed out in the persistent loop");
-        const int q = c->hbctl->parity & 1;
-        bool paused = false, log_full = false;
-        int64_t max_it = 0;
+        bool running = false, log_full = false;
+        int64_t max_it = 0, sum_it = 0;
         for (int j = 0; j < nj; j++) {
-            if (hr[j].donep[q]) continue;
-            paused = true;
-            max_it = hr[j].itp[q] > max_it ? hr[j].itp[q] : max_it;
-            if (with_log && hr[j].itp[q] >= hr[j].log_cap) log_full = true;
+            const Ctl& h = c->hctl[j];
+            sum_it += h.it + (h.done != 0);
+            if (h.done) continue;
+            running = true;
+            max_it = h.it > max_it ? h.it : max_it;
+            if (with_log && h.it >= hb[0].log_cap) log_full = true;
         }
-        if (!paused) break;
-        // parity counts the passes of every launch so far
-        if (max_it > bound || (int64_t)c->hbctl->parity > bound + 1)
-            return fail(c, DMT_E_HIP, "persistent loop exceeded the iteration bound");
-        if (!log_full) continue;   // pass budget of the launch used up: launch again
-        // the log is full: grow it, point the job at it and resume
-        const int64_t host_it = hr[0].itp[q];
+        if (!running) break;
+        if (max_it > bound || sum_it == progress)
+            return fail(c, DMT_E_HIP, "correction loop exceeded the iteration bound or stopped advancing");
+        progress = sum_it;
+        if (!log_full) continue;
+        // the log is full (a single job): grow it, point the job at it and resume
+        const int64_t host_it = c->hctl[0].it;
         TRY(grow_log(c, (size_t)host_it * 2 + 4096, host_it, st));
         hb[0].log = P<long long>(c->dlog);
-        const int cap = (int)(c->dlog.cap / (sizeof(long long) * DMT_LOG_WORDS));
+        hb[0].log_cap = (int)(c->dlog.cap / (sizeof(long long) * DMT_LOG_WORDS));
         HIPCHK(c, hipMemcpyAsync(c->jobs_dev.p, hb.data(), sizeof(FrontierBufs), hipMemcpyHostToDevice, st));
-        HIPCHK(c, hipMemcpyAsync(&P<JobRun>(c->run_dev)->log_cap, &cap, sizeof(int), hipMemcpyHostToDevice, st));
-        HIPCHK(c, hipStreamSynchronize(st));
     }
     return DMT_OK;
 }
@@ -560,7 +605,10 @@ dmt_status run_phases(dmt_context* c, Job& J, hipStream_t st) {
             ProfScope ps(c, DMT_PROF_LOOP, st, 0);
             k_fr_grad<D><<<gfull, TPB, 0, st>>>(J.B, J.dm);
             k_fr_vr<D><<<gfull, TPB, 0, st>>>(J.B, J.dm);
-            if (J.o.tier >= 3) k_fr_sapply<D><<<gfull, TPB, 0, st>>>(J.B, J.dm);
+            if (J.o.tier >= 3) {
+                k_fr_bscan<D><<<gfull, TPB, 0, st>>>(J.B, J.dm);
+                k_fr_sapply<D><<<gfull, TPB, 0, st>>>(J.B, J.dm);
+            }
             k_fr_finish<<<1, 1, 0, st>>>(J.B);
             CHECK_LAUNCH(c);
         }
@@ -568,7 +616,7 @@ dmt_status run_phases(dmt_context* c, Job& J, hipStream_t st) {
         HIPCHK(c, hipStreamSynchronize(st));
         host_it = h.it;
         if (h.done) break;
-        if (host_it > (int64_t)n * (J.o.q_max + 1) + 1)   // the bound of run_persistent
+        if (host_it > (int64_t)n * (J.o.q_max + 1) + 1)   // the bound of run_wg
             return fail(c, DMT_E_HIP, "phase loop exceeded the iteration bound");
         if (batch < 256) batch *= 2;
     }
@@ -730,18 +778,24 @@ dmt_status run_jobs(dmt_context* c, std::vector<Job>& jobs, bool single, hipStre
         TRY(J.D == 2 ? dense_loop<2>(c, J, c->hctl[0], st) : dense_loop<3>(c, J, c->hctl[0], st));
         return job_outputs(c, J, c->hctl[0], true, st);
     }
-    // a2 and frontier state for every live job, then the loop
-    for (Job* J : live) TRY(J->D == 2 ? job_frontier<2>(c, *J, st) : job_frontier<3>(c, *J, st));
+    // a2 and frontier state for every live job (control blocks side by side), then the loop
+    ENSURE(c, c->ctl_all, sizeof(Ctl) * live.size());
+    for (size_t k = 0; k < live.size(); k++) {
+        Ctl* ctl = P<Ctl>(c->ctl_all) + k;
+        TRY(live[k]->D == 2 ? job_frontier<2>(c, *live[k], ctl, st) : job_frontier<3>(c, *live[k], ctl, st));
+    }
     if (single && (jobs[0].o.flags & DMT_F_PHASES)) {
         Job& J = jobs[0];
         TRY(J.D == 2 ? run_phases<2>(c, J, st) : run_phases<3>(c, J, st));
     } else {
         for (Job* J : live) TRY(J->D == 2 ? job_iteration0<2>(c, *J, st) : job_iteration0<3>(c, *J, st));
-        TRY(run_persistent(c, live, single, st));
+        TRY(run_wg(c, live, single, st));
     }
-    for (size_t k = 0; k < live.size(); k++)
-        HIPCHK(c, hipMemcpyAsync(&c->hctl[k], live[k]->B.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipMemcpyAsync(c->hctl.data(), c->ctl_all.p, sizeof(Ctl) * live.size(), hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));
+    for (int k = 0; k < 3; k++) c->ph[k] = 0;
+    for (const Ctl& h : c->hctl)
+        for (int k = 0; k < 3; k++) c->ph[k] += h.ph[k];
     for (size_t k = 0; k < live.size(); k++) TRY(job_outputs(c, *live[k], c->hctl[k], single, st));
     if (single) {
         const int64_t nrec = c->hctl[0].it;
@@ -772,12 +826,10 @@ dmt_status dmt_context_create(dmt_context** ctx, int hip_device) {
     dmt_context* c = new dmt_context();
     c->device = hip_device;
     if (hipHostMalloc((void**)&c->hcnt, sizeof(unsigned long long) * CNT_WORDS, 0) != hipSuccess ||
-        hipHostMalloc((void**)&c->hbctl, sizeof(BatchCtl), 0) != hipSuccess ||
         hipHostMalloc((void**)&c->hscratch, sizeof(int64_t) * 64, 0) != hipSuccess) {
         delete c;
         return DMT_E_NOMEM;
     }
-    *c->hbctl = BatchCtl{};
     *ctx = c;
     return DMT_OK;
 }
@@ -786,7 +838,7 @@ dmt_status dmt_context_destroy(dmt_context* c) {
     if (!c) return DMT_OK;
     (void)hipSetDevice(c->device);
     std::vector<DevBuf*> bufs = {&c->gpl, &c->req, &c->cnt, &c->flags, &c->part, &c->blk, &c->blkoff, &c->ll_idx,
-                                 &c->ll_val, &c->dlog, &c->jobs_dev, &c->dims_dev, &c->run_dev, &c->bctl};
+                                 &c->ll_val, &c->dlog, &c->jobs_dev, &c->ctl_all, &c->queue};
     for (DevBuf* b : c->msc.all()) bufs.push_back(b);
     for (JobWs& w : c->ws)
         for (DevBuf* b : w.all()) bufs.push_back(b);
@@ -794,7 +846,6 @@ dmt_status dmt_context_destroy(dmt_context* c) {
         if (b->p) (void)hipFree(b->p);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     if (c->hcnt) (void)hipHostFree(c->hcnt);
-    if (c->hbctl) (void)hipHostFree(c->hbctl);
     if (c->hscratch) (void)hipHostFree(c->hscratch);
     delete c;
     return DMT_OK;
@@ -1038,10 +1089,11 @@ dmt_status dmt_profile_read(dmt_context* c, int kernel, int64_t* launches, doubl
     *ms_total = ms;
     *units = c->prof_units[kernel];
     if (kernel >= DMT_PROF_LOOP_SAPPLY && kernel <= DMT_PROF_LOOP_VR) {
-        // phases inside the persistent loop: wall-clock ticks (100 MHz) recorded by the kernel
+        // phases inside the resident loop (summed over jobs): wall-clock ticks (100 MHz)
+        // recorded by the kernel during the last correction call
         *launches = 0;
         *units = 0;
-        *ms_total = (double)c->hbctl->ph[kernel - DMT_PROF_LOOP_SAPPLY] * 1e-5;
+        *ms_total = (double)c->ph[kernel - DMT_PROF_LOOP_SAPPLY] * 1e-5;
     }
     return DMT_OK;
 }

@@ -218,8 +218,10 @@ __device__ __forceinline__ void grad_vertex(const int v, const float* __restrict
         const int dx = g.slot_d[s][0], dy = g.slot_d[s][1], dz = g.slot_d[s][2];
         const bool ok = (unsigned)(x + dx) < (unsigned)dm.nx && (unsigned)(y + dy) < (unsigned)dm.ny &&
                         (unsigned)(z + dz) < (unsigned)dm.nz;
-        hn[s] = 0.0f;
-        if (ok) hn[s] = h[v + dx + dm.nx * dy + dm.nxy * dz];
+        // unconditional load (a neighbour outside the grid reads v itself) so that all loads are
+        // issued together; its value is then replaced by 0 and never used (L excludes it)
+        const float hs = h[ok ? v + dx + dm.nx * dy + dm.nxy * dz : v];
+        hn[s] = ok ? hs : 0.0f;
         // neighbour ids below v's are in slots < FULL: they win ties
         const bool lw = s < FULL ? (hn[s] <= hv) : (hn[s] < hv);
         L |= (uint32_t)(ok && lw) << s;
@@ -530,6 +532,44 @@ __global__ void __launch_bounds__(1024) k_scan_single(const int* __restrict__ in
     __syncthreads();
     long long acc = part[threadIdx.x];
     for (int64_t i = b; i < e; i++) { out[i] = acc; acc += in[i]; }
+}
+
+// Exclusive scan of int counts in tiles of 1024 (256 threads x 4 consecutive elements).
+// k_tile_sum: tsum[t] = sum of tile t.  k_tile_scan, given toff = exclusive scan of tsum
+// (toff[ntiles] = total): out[i] = exclusive prefix of in at i, out[n] = total; in is
+// overwritten with the same offsets (fill positions for a counting sort).
+__global__ void __launch_bounds__(256) k_tile_sum(const int* __restrict__ in, int n, int* __restrict__ tsum) {
+    const int i0 = blockIdx.x * 1024 + threadIdx.x * 4;
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < 4; k++)
+        if (i0 + k < n) s += in[i0 + k];
+    int total = 0;
+    (void)block_exclusive_scan(s, total);
+    if (threadIdx.x == 0) tsum[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(256) k_tile_scan(int* __restrict__ in, int n, const int64_t* __restrict__ toff,
+                                                   int* __restrict__ out) {
+    const int i0 = blockIdx.x * 1024 + threadIdx.x * 4;
+    int v[4];
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        v[k] = i0 + k < n ? in[i0 + k] : 0;
+        s += v[k];
+    }
+    int total = 0;
+    int acc = (int)toff[blockIdx.x] + block_exclusive_scan(s, total);
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        if (i0 + k < n) {
+            out[i0 + k] = acc;
+            in[i0 + k] = acc;
+        }
+        acc += v[k];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = (int)toff[gridDim.x];
 }
 
 // ----------------------------------------------------------------------------------------

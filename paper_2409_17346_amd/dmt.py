@@ -22,9 +22,10 @@ DMT_OK = 0
 DMT_W_NOT_CONVERGED = 1
 STATUS_NAMES = {0: "ok", 1: "not_converged", -1: "invalid", -2: "bound", -3: "nonfinite", -4: "nomem",
                 -5: "hip"}
-LOG_WORDS = 16
+LOG_WORDS = 20
 LOG_KEYS = ["kind", "FP0", "FN0", "FP1", "FN1", "FP2", "FN2", "FP3", "FN3", "TM_desc", "TM_asc", "n_req",
-            "changed"]
+            "changed", "dirty_vertices", "affected_anchors", "listed_anchors", "branches_settled",
+            "branch_cells_examined", "branch_cells_touched", "ticks"]
 
 MSC_ITEMS = {
     "crit0": 0, "crit1": 1, "crit2": 2, "crit3": 3,
