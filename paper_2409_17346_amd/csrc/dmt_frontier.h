@@ -36,7 +36,8 @@ struct Slot {
 
 struct Ctl {
     int it;                 // current iteration
-    int done;               // 0 running, 1 converged, 2 iteration cap, 3 stalled, 4 paused (log full)
+    int done;               // 0 running, 1 converged, 2 iteration cap, 3 stalled
+    int paused;             // 1: the resident loop stopped before a large iteration (host runs it)
     int c_it, s_it;
     long long residual;
     unsigned long long ph[3];   // wall-clock ticks in the resident loop: troublemaker, gradient, violation passes
@@ -669,6 +670,7 @@ __device__ __forceinline__ void record_iteration(const FrontierView& B, int it, 
 __global__ void k_fr_init(Ctl* c) {
     c->it = 0;
     c->done = 0;
+    c->paused = 0;
     c->c_it = c->s_it = 0;
     c->residual = 0;
     c->ph[0] = c->ph[1] = c->ph[2] = 0;
@@ -681,12 +683,55 @@ __global__ void k_fr_init(Ctl* c) {
 
 // ---- workgroup-resident form: each job's loop runs inside one workgroup ---------------------
 
+// iteration_state and record_iteration for a whole wave (wave 0 of the workgroup): lane k
+// loads counter k, so the loads are issued together, and writes log word k.
+__device__ __forceinline__ int wave_decide(const FrontierView& B, int it, int lane) {
+    const Slot& S = slot_of(B, it);
+    const unsigned long long v = lane < CNT_WORDS ? ld_relaxed(&S.cnt[lane]) : 0ull;
+    const unsigned long long cv = (lane >= CNT_FP0 && lane < CNT_FP0 + 8) ? v : 0ull;
+    const unsigned long long tv = (lane == CNT_TM_DESC || lane == CNT_TM_ASC) ? v : 0ull;
+    unsigned long long ct = cv, tt = tv;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        ct += __shfl_xor(ct, o, 64);
+        tt += __shfl_xor(tt, o, 64);
+    }
+    const unsigned long long changed = __shfl(v, CNT_CHANGED, 64);
+    const unsigned long long viol = ct ? ct : (B.tier >= 3 ? tt : 0ull);
+    int st = 0;
+    if (viol == 0) st = 1;
+    else if ((long long)it == B.max_iters) st = 2;
+    else if (changed == 0) st = 3;
+    Ctl* c = B.ctl;
+    if (st == 0 && B.log) {
+        long long* rec = B.log + (size_t)it * DMT_LOG_WORDS;
+        if (lane == 0) rec[0] = ct ? 1 : 2;
+        else if (lane < CNT_WORDS && lane <= CNT_CHANGED) rec[lane] = (long long)v;
+        else if (lane == 13) rec[13] = ld_relaxed(&S.n_dv);
+        else if (lane == 14) rec[14] = ld_relaxed(&S.n_da);
+        else if (lane == 15) rec[15] = ld_relaxed(&S.n_vl);
+        else if (lane == 16) rec[16] = ld_relaxed(&S.n_db);
+        else if (lane == 17) rec[17] = ld_relaxed(&S.n_scan);
+        else if (lane == 18) rec[18] = ld_relaxed(&S.n_tc);
+    }
+    if (lane == 0) {
+        if (st == 2 || st == 3) c->residual = (long long)viol;
+        if (st == 0) {
+            if (ct) c->c_it++;
+            else c->s_it++;
+        }
+    }
+    return st;
+}
+
 // The loop of one job from the end of its iteration ctl->it's violation pass (the
-// precondition: that iteration's gradient and violation passes are done), in one workgroup,
-// synchronised by workgroup barriers only.  Returns when the job ends, when its log is full
-// or after max_passes iterations; the host launches it again in the last two cases.
+// precondition: that iteration's gradient, violation and branch passes are done), in one
+// workgroup, synchronised by workgroup barriers only.  Returns when the job ends, when its log
+// is full, after max_passes iterations, or (big > 0) before an iteration with more than big
+// affected and listed anchors, with ctl->paused set and ctl->it that iteration, whose passes
+// have not started; the host runs such iterations as full-grid launches.
 template <int D>
-__device__ __forceinline__ void run_job_wg(const FrontierView& B, int max_passes) {
+__device__ __forceinline__ void run_job_wg(const FrontierView& B, int max_passes, int big) {
     const Dims dm = B.dm;
     Ctl* c = B.ctl;
     const int tid = threadIdx.x, nt = blockDim.x;
@@ -713,13 +758,21 @@ __device__ __forceinline__ void run_job_wg(const FrontierView& B, int max_passes
             __syncthreads();
         }
         if (tid < 64) {
-            const int st = iteration_state(B, it);
+            const int st = wave_decide(B, it, tid);
             if (tid == 0) {
-                record_iteration(B, it, st);
                 if (B.log && st == 0) B.log[(size_t)it * DMT_LOG_WORDS + 19] = (long long)(wall_clock64() - t_it);
                 c->it = st ? it : it + 1;
                 c->done = st;
-                state_sh = st;
+                int act = st;
+                // a large next iteration is left to full-grid launches: pause before its gradient pass
+                if (st == 0 && big > 0) {
+                    const Slot& N = slot_of(B, it + 1);
+                    if (ld_relaxed(&N.n_da) + ld_relaxed(&N.n_vl) > big) {
+                        c->paused = 1;
+                        act = 4;
+                    }
+                }
+                state_sh = act;
             }
         }
         __syncthreads();
@@ -754,7 +807,7 @@ struct WgThreads {
 // until none is left.
 template <int D>
 __global__ void __launch_bounds__(WgThreads<D>::value) k_fr_loop_wg(const FrontierBufs* __restrict__ jobs,
-                                                                    int n_jobs, int* queue, int max_passes) {
+                                                                    int n_jobs, int* queue, int max_passes, int big) {
     __shared__ int job_sh;
     for (;;) {
         if (threadIdx.x == 0) job_sh = atomicAdd(queue, 1);
@@ -762,7 +815,7 @@ __global__ void __launch_bounds__(WgThreads<D>::value) k_fr_loop_wg(const Fronti
         const int j = __builtin_amdgcn_readfirstlane(job_sh);   // uniform: job fields load as scalars
         __syncthreads();
         if (j >= n_jobs) return;
-        run_job_wg<D>(view(jobs[j]), max_passes);
+        run_job_wg<D>(view(jobs[j]), max_passes, big);
     }
 }
 

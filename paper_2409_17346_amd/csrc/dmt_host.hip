@@ -507,6 +507,24 @@ dmt_status grow_log(dmt_context* c, size_t need, int64_t keep, hipStream_t st) {
     return DMT_OK;
 }
 
+// K iterations of one job as full-grid launches (one per phase) from the start of iteration
+// ctl->it, then the gradient, violation and branch passes of the next one: the state the
+// resident loop starts from.  Launches of a finished job return at once.
+template <int D>
+dmt_status grid_iterations(dmt_context* c, const FrontierBufs& B, const Dims& dm, int K, hipStream_t st) {
+    const unsigned gfull = nblocks(dm.n) < 2048u ? nblocks(dm.n) : 2048u;
+    for (int k = 0; k <= K; k++) {
+        k_fr_grad<D><<<gfull, TPB, 0, st>>>(B, dm);
+        k_fr_vr<D><<<gfull, TPB, 0, st>>>(B, dm);
+        if (B.tier >= 3) k_fr_bscan<D><<<gfull, TPB, 0, st>>>(B, dm);
+        if (k == K) break;
+        if (B.tier >= 3) k_fr_sapply<D><<<gfull, TPB, 0, st>>>(B, dm);
+        k_fr_finish<<<1, 1, 0, st>>>(B);
+    }
+    CHECK_LAUNCH(c);
+    return DMT_OK;
+}
+
 // The loops of the jobs in workgroup-resident form: one launch per dimension present, one
 // workgroup per job at a time.  A single job may keep a log; its loop pauses when the log is
 // full and is launched again after the log has grown.  Every launch ends after a bounded
@@ -545,6 +563,14 @@ dmt_status run_wg(dmt_context* c, std::vector<Job*>& jobs, bool with_log, hipStr
     }
     HIPCHK(c, hipMemcpyAsync(c->jobs_dev.p, hb.data(), sizeof(FrontierBufs) * nj, hipMemcpyHostToDevice, st));
     const int max_passes = 1 << 18;
+    // a single job hands iterations with more than `big` affected and listed anchors to
+    // full-grid launches (a workgroup takes about 1 us per 100 such anchors, the grid far less)
+    int big = 0;
+    if (nj == 1) {
+        big = 8192;
+        if (const char* e = getenv("DMT_WG_MAX_ANCHORS")) big = atoi(e);
+    }
+    const int grid_batch = 4;
     int64_t progress = -1;
     for (;;) {
         HIPCHK(c, hipMemsetAsync(c->queue.p, 0, sizeof(int) * 2, st));
@@ -553,13 +579,13 @@ dmt_status run_wg(dmt_context* c, std::vector<Job*>& jobs, bool with_log, hipStr
             const FrontierBufs* jd = P<FrontierBufs>(c->jobs_dev);
             if (n2) {
                 const int blocks = n2 < ncu * occ2 ? n2 : ncu * occ2;
-                k_fr_loop_wg<2><<<blocks, WgThreads<2>::value, 0, st>>>(jd, n2, P<int>(c->queue), max_passes);
+                k_fr_loop_wg<2><<<blocks, WgThreads<2>::value, 0, st>>>(jd, n2, P<int>(c->queue), max_passes, big);
                 CHECK_LAUNCH(c);
             }
             if (nj > n2) {
                 const int blocks = nj - n2 < ncu * occ3 ? nj - n2 : ncu * occ3;
                 k_fr_loop_wg<3><<<blocks, WgThreads<3>::value, 0, st>>>(jd + n2, nj - n2, P<int>(c->queue) + 1,
-                                                                         max_passes);
+                                                                         max_passes, big);
                 CHECK_LAUNCH(c);
             }
         }
@@ -579,6 +605,24 @@ dmt_status run_wg(dmt_context* c, std::vector<Job*>& jobs, bool with_log, hipStr
         if (max_it > bound || sum_it == progress)
             return fail(c, DMT_E_HIP, "correction loop exceeded the iteration bound or stopped advancing");
         progress = sum_it;
+        if (nj == 1 && c->hctl[0].paused) {
+            // a large iteration: run a few as full-grid launches, with room in the log for them
+            const Job* J = jobs[0];
+            const int64_t it0 = c->hctl[0].it;
+            if (with_log && it0 + grid_batch + 2 > hb[0].log_cap) {
+                TRY(grow_log(c, (size_t)(it0 + grid_batch) * 2 + 4096, it0, st));
+                hb[0].log = P<long long>(c->dlog);
+                hb[0].log_cap = (int)(c->dlog.cap / (sizeof(long long) * DMT_LOG_WORDS));
+                HIPCHK(c, hipMemcpyAsync(c->jobs_dev.p, hb.data(), sizeof(FrontierBufs), hipMemcpyHostToDevice, st));
+            }
+            HIPCHK(c, hipMemsetAsync(&J->B.ctl->paused, 0, sizeof(int), st));
+            {
+                ProfScope ps(c, DMT_PROF_LOOP, st, 0);
+                TRY(J->D == 2 ? grid_iterations<2>(c, hb[0], J->dm, grid_batch, st)
+                              : grid_iterations<3>(c, hb[0], J->dm, grid_batch, st));
+            }
+            continue;
+        }
         if (!log_full) continue;
         // the log is full (a single job): grow it, point the job at it and resume
         const int64_t host_it = c->hctl[0].it;

@@ -159,6 +159,25 @@ def test_correct_large2d_crop(ctx, dmt, flags):
     assert r.status == "ok" and r.stats["s_iterations"] > 100
 
 
+@pytest.mark.parametrize("limit", [1, 8, 64])
+@pytest.mark.parametrize("case", ["small2d", "tiny3d", "crop2d"])
+def test_correct_hybrid_handoff(ctx, dmt, monkeypatch, limit, case):
+    """Iterations with more affected + listed anchors than the limit leave the resident loop for
+    full-grid launches and come back: results and log stay those of the oracle."""
+    if case == "small2d":
+        w = synth.config_small2d()
+    elif case == "tiny3d":
+        w = synth.tiny_cases(13, (12, 10, 9), rel=0.05, kind="smooth", ghat="noise")
+    else:
+        w = synth.config_large2d()
+        w.f = np.ascontiguousarray(w.f[:96, :128])
+        w.g_hat = np.ascontiguousarray(w.g_hat[:96, :128])
+    monkeypatch.setenv("DMT_WG_MAX_ANCHORS", str(limit))
+    r, o = _compare_correction(ctx, dmt, w)
+    log = r.log.numpy()
+    assert (log[:, 14] + log[:, 15] > limit).any(), "the hand-off was not exercised"
+
+
 def _floor_collision_inversions(w, g):
     """Adjacent vertex pairs that are both at their floor, with equal floors, in the opposite
     order to f: decrease-only edits can never separate them (fp32 floors f - xi rounded up
