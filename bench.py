@@ -109,12 +109,66 @@ def cpu_baseline(w, crop: int):
                       f"to convergence ({r['stats']['iterations']} iterations) in {dt:.1f} s on one host thread"}
 
 
+def bench_batch(args):
+    """The batched form: a step is one dmt_correct_batch call over 64 uneven fields (32 2D with
+    side log-uniform in [256, 1024], 32 3D with side log-uniform in [64, 160], xi from
+    {1e-3, 1e-4} * range, g_hat binned or noisy)."""
+    import numpy as np
+    import torch
+    from paper_2409_17346_amd import dmt, synth
+    ws = synth.batch_mix(0, 64)
+    n_total = sum(w.f.size for w in ws)
+    print(f"[bench] batch of {len(ws)} fields, {n_total} vertices", file=sys.stderr, flush=True)
+    ctx = dmt.Context(0)
+    fields = [(torch.from_numpy(w.f).cuda(), torch.from_numpy(w.g_hat).cuda(), w.xi) for w in ws]
+    outs = [(torch.empty_like(f), torch.empty(f.shape, dtype=torch.uint8, device="cuda")) for f, _, _ in fields]
+    for i in range(args.warmup):
+        res = dmt.dmt_correct_batch(ctx, fields, outputs=outs)
+        print(f"[bench] warmup {i}: " + str({s: sum(r.status == s for r in res) for s in set(r.status for r in res)}),
+              file=sys.stderr, flush=True)
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ts = time.perf_counter()
+        res = dmt.dmt_correct_batch(ctx, fields, outputs=outs)
+        lat.append(time.perf_counter() - ts)
+        print(f"[bench] step {i}: {lat[-1] * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    dmt.dmt_profile_enable(ctx, True)
+    res = dmt.dmt_correct_batch(ctx, fields, outputs=outs)
+    prof = dmt.dmt_profile_read(ctx)
+    dmt.dmt_profile_enable(ctx, False)
+    lat_sorted = sorted(lat)
+
+    def pct(p):
+        k = min(len(lat_sorted) - 1, max(0, int(round(p / 100.0 * (len(lat_sorted) - 1)))))
+        return round(lat_sorted[k] * 1e3, 3)
+
+    status = {s: sum(r.status == s for r in res) for s in sorted(set(r.status for r in res))}
+    iters = [r.stats["iterations"] for r in res]
+    line = {
+        "metric": METRIC, "value": round(4.0 * n_total * args.steps / elapsed / 1e6, 3), "unit": "MB/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batch64-mixed-2d256-1024-3d64-160", "fields": len(ws), "vertices": n_total,
+                   "tier": 4, "q_max": 6, "status": status, "iterations_max": max(iters),
+                   "iterations_median": int(np.median(iters))},
+        "latency_ms": {"p50": pct(50), "p99": pct(99)},
+        "kernel_ms": {k: round(v["ms"], 3) for k, v in prof.items()},
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="large2d", choices=["large2d", "small2d", "atoms3d"])
+    ap.add_argument("--workload", default="large2d", choices=["large2d", "small2d", "atoms3d", "batch64"])
     ap.add_argument("--cpu-crop", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--flags", type=int, default=0, help="dmt_options.flags (1 dense loop, 2 one launch per phase)")
@@ -132,6 +186,8 @@ def main():
 
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
+    if args.workload == "batch64":
+        return bench_batch(args)
     if args.copy_probe_mib > 0:
         src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

@@ -38,6 +38,8 @@ struct Ctl {
     int it;                 // current iteration
     int done;               // 0 running, 1 converged, 2 iteration cap, 3 stalled
     int paused;             // 1: the resident loop stopped before a large iteration (host runs it)
+    int cand_sel;           // current troublemaker candidate list (cand[cand_sel])
+    int n_cand[2];
     int c_it, s_it;
     long long residual;
     unsigned long long ph[3];   // wall-clock ticks in the resident loop: troublemaker, gradient, violation passes
@@ -99,6 +101,10 @@ struct Ctl {
     P(int) tcl;               /* touched cells of the current iteration */                         \
     P(int) dbl;               /* touched branches of the current iteration */                      \
     P(int) newmin;            /* per branch id: first touched cell that differs (INF32 between) */ \
+    /* branches whose first differing cell may be set (a superset of them), for the separatrix    \
+       step; inlist marks the members */                                                           \
+    P(int) cand[2];                                                                                \
+    P(uint8_t) inlist;                                                                             \
     float delta;                                                                                   \
     int q_max, tier;                                                                               \
     long long max_iters;
@@ -473,6 +479,7 @@ __device__ __forceinline__ void phase_bscan(const FrontierView& B, const Dims& d
     Slot& S = slot_of(B, it);
     const int n = ld_relaxed(&S.n_db);
     const int lane = __lane_id();
+    const int sel = ld_relaxed(&B.ctl->cand_sel);
     int scanned = 0;
     for (int i = gtid >> 6; i < n; i += gsize >> 6) {
         const int bb = B.dbl[i];
@@ -504,6 +511,10 @@ __device__ __forceinline__ void phase_bscan(const FrontierView& B, const Dims& d
         if (lane == 0) {
             first[b] = res;
             B.newmin[bb] = INF32;
+            if (res != INF32 && !B.inlist[bb]) {
+                B.inlist[bb] = 1;
+                B.cand[sel][atomicAdd(&B.ctl->n_cand[sel], 1)] = bb;
+            }
         }
     }
     if (lane == 0 && scanned) atomicAdd(&S.n_scan, scanned);
@@ -573,19 +584,29 @@ __device__ __forceinline__ void phase_sapply(const FrontierView& B, const Dims& 
     constexpr auto& g = G<D>::g;
     int c[2] = {0, 0};
     int rc[2] = {0, 0};
-    const int nb = B.n_desc + B.n_asc;
+    // the candidate list: members whose first differing cell is unset leave it, the others are
+    // kept in the other buffer (the decision of this iteration makes it current)
+    const int sel = ld_relaxed(&B.ctl->cand_sel);
+    const int nb = ld_relaxed(&B.ctl->n_cand[sel]);
+    const int* cl = B.cand[sel];
+    int* keep = B.cand[sel ^ 1];
     for (int base = 0; base < nb; base += gsize) {
         if (wave_done(base, gtid, nb)) break;
         const int i0 = base + gtid;
         int target = -1;
+        bool kept = false;
+        int bb = 0;
         if (i0 < nb) {
-            const bool asc = i0 >= B.n_desc;
-            const int b = asc ? i0 - B.n_desc : i0;
+            bb = cl[i0];
+            const bool asc = bb >= B.n_desc;
+            const int b = asc ? bb - B.n_desc : bb;
             const int* first = asc ? B.afirst : B.dfirst;
             const int* cells = asc ? B.acell : B.dcell;
             const int64_t* off = asc ? B.aoff : B.doff;
             const int* term = asc ? B.aterm : B.dterm;
             const int k = first[b];
+            kept = k != INF32;
+            if (!kept) B.inlist[bb] = 0;
             if (k != INF32) {
                 bool ok = true;
                 if (B.tier == 3) {
@@ -625,6 +646,8 @@ __device__ __forceinline__ void phase_sapply(const FrontierView& B, const Dims& 
                 }
             }
         }
+        const int idx = wave_append(kept, &B.ctl->n_cand[sel ^ 1]);
+        if (kept) keep[idx] = bb;
         request_apply<D>(B, dm, target, it, edit, rc);
     }
     block_add_counters<2>(slot_of(B, it).cnt + CNT_TM_DESC, c);
@@ -667,10 +690,28 @@ __device__ __forceinline__ void record_iteration(const FrontierView& B, int it, 
     if (cstep) c->c_it++; else c->s_it++;
 }
 
+// Every branch starts as a candidate (list 0).
+__global__ void __launch_bounds__(256) k_fr_cand_init(FrontierBufs hb, Ctl* c) {
+    const FrontierView& B = view(hb);
+    const int nb = B.n_desc + B.n_asc;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nb) {
+        B.cand[0][i] = i;
+        B.inlist[i] = 1;
+    }
+    if (i == 0) {
+        c->cand_sel = 0;
+        c->n_cand[0] = nb;
+        c->n_cand[1] = 0;
+    }
+}
+
 __global__ void k_fr_init(Ctl* c) {
     c->it = 0;
     c->done = 0;
     c->paused = 0;
+    c->cand_sel = 0;
+    c->n_cand[0] = c->n_cand[1] = 0;
     c->c_it = c->s_it = 0;
     c->residual = 0;
     c->ph[0] = c->ph[1] = c->ph[2] = 0;
@@ -682,6 +723,13 @@ __global__ void k_fr_init(Ctl* c) {
 }
 
 // ---- workgroup-resident form: each job's loop runs inside one workgroup ---------------------
+
+// After a separatrix step: the list its troublemaker pass kept becomes current (one thread).
+__device__ __forceinline__ void cand_flip(Ctl* c) {
+    const int sel = c->cand_sel;
+    c->n_cand[sel] = 0;
+    c->cand_sel = sel ^ 1;
+}
 
 // iteration_state and record_iteration for a whole wave (wave 0 of the workgroup): lane k
 // loads counter k, so the loads are issued together, and writes log word k.
@@ -720,6 +768,7 @@ __device__ __forceinline__ int wave_decide(const FrontierView& B, int it, int la
             if (ct) c->c_it++;
             else c->s_it++;
         }
+        if (ct == 0 && B.tier >= 3) cand_flip(c);
     }
     return st;
 }
@@ -899,6 +948,7 @@ __global__ void k_fr_finish(FrontierBufs hb) {
     const int it = c->it;
     const int state = iteration_state(B, it);
     record_iteration(B, it, state);
+    if (B.tier >= 3 && c_total(slot_of(B, it)) == 0) cand_flip(c);
     if (state) { c->done = state; return; }
     c->it = it + 1;
 }

@@ -46,13 +46,13 @@ struct MscBufs {
 // Device state of one correction job.
 struct JobWs {
     DevBuf lo, g0, g1, state, fpl, gpl, vmask, vl0, vl1, dvl0, dvl1, dal0, dal1, vstamp, astamp, astamp1, rstamp;
-    DevBuf vpos, vstart, tsum, toff, ecell, bstamp, tcl, dbl, newmin;
+    DevBuf vpos, vstart, tsum, toff, ecell, bstamp, tcl, dbl, newmin, cand0, cand1, inlist;
     MscBufs msc;
     std::vector<DevBuf*> all() {
         std::vector<DevBuf*> v = {&lo,     &g0,     &g1,      &state,  &fpl,   &gpl,   &vmask,  &vl0,
                                   &vl1,    &dvl0,   &dvl1,    &dal0,   &dal1,  &vstamp, &astamp, &astamp1,
                                   &rstamp, &vpos,   &vstart,  &tsum,   &toff,   &ecell, &bstamp, &tcl,
-                                  &dbl,    &newmin};
+                                  &dbl,    &newmin, &cand0,   &cand1,  &inlist};
         for (DevBuf* b : msc.all()) v.push_back(b);
         return v;
     }
@@ -71,6 +71,8 @@ struct dmt_context {
     unsigned long long* hcnt = nullptr;    // pinned
     int64_t* hscratch = nullptr;           // pinned
     std::vector<Ctl> hctl;                 // per-job control blocks read back after the loop
+    hipStream_t side = nullptr;            // the 3D loop kernel of a mixed batch runs here
+    hipEvent_t fork = nullptr, join = nullptr;
     unsigned long long ph[3] = {0, 0, 0};  // loop phase ticks of the last correction call
     // kernel timing: event pairs per kernel family, recorded on the launch stream
     bool prof = false;
@@ -442,6 +444,9 @@ dmt_status job_frontier(dmt_context* c, Job& J, Ctl* ctl, hipStream_t st) {
         ENSURE(c, w.bstamp, sizeof(unsigned) * (size_t)nbr);
         ENSURE(c, w.dbl, sizeof(int) * (size_t)nbr);
         ENSURE(c, w.newmin, sizeof(int) * (size_t)nbr);
+        ENSURE(c, w.cand0, sizeof(int) * (size_t)nbr);
+        ENSURE(c, w.cand1, sizeof(int) * (size_t)nbr);
+        ENSURE(c, w.inlist, (size_t)nbr);
         TRY(fill_i32(c, P<int>(w.newmin), nbr, INF32, st));
         HIPCHK(c, hipMemsetAsync(w.vpos.p, 0, sizeof(int) * n, st));
         HIPCHK(c, hipMemsetAsync(w.bstamp.p, 0, sizeof(unsigned) * (size_t)nbr, st));
@@ -465,6 +470,13 @@ dmt_status job_frontier(dmt_context* c, Job& J, Ctl* ctl, hipStream_t st) {
         B.tcl = P<int>(w.tcl);
         B.dbl = P<int>(w.dbl);
         B.newmin = P<int>(w.newmin);
+        B.cand[0] = P<int>(w.cand0);
+        B.cand[1] = P<int>(w.cand1);
+        B.inlist = P<uint8_t>(w.inlist);
+        if (nbr) {
+            k_fr_cand_init<<<nblocks(nbr), TPB, 0, st>>>(B, ctl);
+            CHECK_LAUNCH(c);
+        }
     }
     B.delta = ldexpf(J.xi, -J.o.q_max);
     B.q_max = J.o.q_max;
@@ -563,20 +575,38 @@ dmt_status run_wg(dmt_context* c, std::vector<Job*>& jobs, bool with_log, hipStr
     }
     HIPCHK(c, hipMemcpyAsync(c->jobs_dev.p, hb.data(), sizeof(FrontierBufs) * nj, hipMemcpyHostToDevice, st));
     const int max_passes = 1 << 18;
-    // a single job hands iterations with more than `big` affected and listed anchors to
-    // full-grid launches (a workgroup takes about 1 us per 100 such anchors, the grid far less)
-    int big = 0;
-    if (nj == 1) {
-        big = 8192;
-        if (const char* e = getenv("DMT_WG_MAX_ANCHORS")) big = atoi(e);
-    }
-    const int grid_batch = 4;
+    // iterations with more than `big` affected and listed anchors are handed to full-grid
+    // launches (a workgroup takes about 1 us per 100 such anchors, the grid far less); the loop
+    // kernel ends once every job has finished or paused, then the host runs a few iterations of
+    // each paused job on the whole grid and launches the loop again
+    int big = 8192;
+    if (const char* e = getenv("DMT_WG_MAX_ANCHORS")) big = atoi(e);
+    std::vector<int> pos(nj);
+    for (int k = 0; k < nj; k++) pos[order[k]] = k;
+    // a paused job of a batch waits for every other workgroup to finish or pause before the
+    // host can run its grid iterations, so batches hand over more iterations at a time
+    int grid_batch = nj == 1 ? 4 : 64;
+    if (const char* e = getenv("DMT_GRID_BATCH")) grid_batch = atoi(e) > 0 ? atoi(e) : grid_batch;
     int64_t progress = -1;
     for (;;) {
         HIPCHK(c, hipMemsetAsync(c->queue.p, 0, sizeof(int) * 2, st));
         {
             ProfScope ps(c, DMT_PROF_LOOP, st, 0);
             const FrontierBufs* jd = P<FrontierBufs>(c->jobs_dev);
+            // 3D jobs of a mixed batch run beside the 2D ones, on the context's second stream,
+            // forked from st before either launch and joined back into st after both
+            const bool mixed = n2 > 0 && nj > n2;
+            hipStream_t s3 = st;
+            if (mixed) {
+                if (!c->side) {
+                    HIPCHK(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+                    HIPCHK(c, hipEventCreateWithFlags(&c->fork, hipEventDisableTiming));
+                    HIPCHK(c, hipEventCreateWithFlags(&c->join, hipEventDisableTiming));
+                }
+                HIPCHK(c, hipEventRecord(c->fork, st));
+                HIPCHK(c, hipStreamWaitEvent(c->side, c->fork, 0));
+                s3 = c->side;
+            }
             if (n2) {
                 const int blocks = n2 < ncu * occ2 ? n2 : ncu * occ2;
                 k_fr_loop_wg<2><<<blocks, WgThreads<2>::value, 0, st>>>(jd, n2, P<int>(c->queue), max_passes, big);
@@ -584,9 +614,13 @@ dmt_status run_wg(dmt_context* c, std::vector<Job*>& jobs, bool with_log, hipStr
             }
             if (nj > n2) {
                 const int blocks = nj - n2 < ncu * occ3 ? nj - n2 : ncu * occ3;
-                k_fr_loop_wg<3><<<blocks, WgThreads<3>::value, 0, st>>>(jd + n2, nj - n2, P<int>(c->queue) + 1,
+                k_fr_loop_wg<3><<<blocks, WgThreads<3>::value, 0, s3>>>(jd + n2, nj - n2, P<int>(c->queue) + 1,
                                                                          max_passes, big);
                 CHECK_LAUNCH(c);
+            }
+            if (mixed) {
+                HIPCHK(c, hipEventRecord(c->join, c->side));
+                HIPCHK(c, hipStreamWaitEvent(st, c->join, 0));
             }
         }
         HIPCHK(c, hipMemcpyAsync(c->hctl.data(), c->ctl_all.p, sizeof(Ctl) * nj, hipMemcpyDeviceToHost, st));
@@ -605,24 +639,27 @@ dmt_status run_wg(dmt_context* c, std::vector<Job*>& jobs, bool with_log, hipStr
         if (max_it > bound || sum_it == progress)
             return fail(c, DMT_E_HIP, "correction loop exceeded the iteration bound or stopped advancing");
         progress = sum_it;
-        if (nj == 1 && c->hctl[0].paused) {
+        bool any_paused = false;
+        for (int j = 0; j < nj; j++) {
+            if (c->hctl[j].done || !c->hctl[j].paused) continue;
             // a large iteration: run a few as full-grid launches, with room in the log for them
-            const Job* J = jobs[0];
-            const int64_t it0 = c->hctl[0].it;
-            if (with_log && it0 + grid_batch + 2 > hb[0].log_cap) {
+            any_paused = true;
+            const Job* J = jobs[j];
+            FrontierBufs& hj = hb[pos[j]];
+            const int64_t it0 = c->hctl[j].it;
+            if (with_log && it0 + grid_batch + 2 > hj.log_cap) {
                 TRY(grow_log(c, (size_t)(it0 + grid_batch) * 2 + 4096, it0, st));
-                hb[0].log = P<long long>(c->dlog);
-                hb[0].log_cap = (int)(c->dlog.cap / (sizeof(long long) * DMT_LOG_WORDS));
-                HIPCHK(c, hipMemcpyAsync(c->jobs_dev.p, hb.data(), sizeof(FrontierBufs), hipMemcpyHostToDevice, st));
+                hj.log = P<long long>(c->dlog);
+                hj.log_cap = (int)(c->dlog.cap / (sizeof(long long) * DMT_LOG_WORDS));
+                HIPCHK(c, hipMemcpyAsync(P<FrontierBufs>(c->jobs_dev) + pos[j], &hj, sizeof(FrontierBufs),
+                                         hipMemcpyHostToDevice, st));
             }
             HIPCHK(c, hipMemsetAsync(&J->B.ctl->paused, 0, sizeof(int), st));
-            {
-                ProfScope ps(c, DMT_PROF_LOOP, st, 0);
-                TRY(J->D == 2 ? grid_iterations<2>(c, hb[0], J->dm, grid_batch, st)
-                              : grid_iterations<3>(c, hb[0], J->dm, grid_batch, st));
-            }
-            continue;
+            ProfScope ps(c, DMT_PROF_LOOP, st, 0);
+            TRY(J->D == 2 ? grid_iterations<2>(c, hj, J->dm, grid_batch, st)
+                          : grid_iterations<3>(c, hj, J->dm, grid_batch, st));
         }
+        if (any_paused) continue;
         if (!log_full) continue;
         // the log is full (a single job): grow it, point the job at it and resume
         const int64_t host_it = c->hctl[0].it;
@@ -889,6 +926,9 @@ dmt_status dmt_context_destroy(dmt_context* c) {
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    if (c->fork) (void)hipEventDestroy(c->fork);
+    if (c->join) (void)hipEventDestroy(c->join);
+    if (c->side) (void)hipStreamDestroy(c->side);
     if (c->hcnt) (void)hipHostFree(c->hcnt);
     if (c->hscratch) (void)hipHostFree(c->hscratch);
     delete c;
