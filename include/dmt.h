@@ -48,6 +48,7 @@ extern "C" {
 typedef enum {
     DMT_OK = 0,
     DMT_W_NOT_CONVERGED = 1,   /* stalled or iteration cap hit; outputs valid and within bound */
+    DMT_W_PENDING = 2,         /* dmt_server_poll: the job has not finished yet */
     DMT_E_INVALID = -1,        /* bad grid, options, xi or sizes */
     DMT_E_BOUND = -2,          /* some |g_hat_i - f_i| > xi */
     DMT_E_NONFINITE = -3,      /* NaN or Inf in an input field */
@@ -199,6 +200,38 @@ typedef struct {
  * lossless edits of a job are the vertices whose q_out is 0xFF, with values g_out; no
  * per-iteration log is kept. */
 dmt_status dmt_correct_batch(dmt_context *ctx, int32_t n_jobs, dmt_job *jobs_host, hipStream_t stream);
+
+/* ---- served form: a request stream of corrections --------------------------------------- */
+
+/* Estimated device workspace (bytes) of correcting one field of this grid: the unit of the
+ * server's admission.  An upper estimate (the separatrix branches are data-dependent); -1 for an
+ * invalid grid. */
+int64_t dmt_workspace_bytes(const dmt_grid *grid, const dmt_options *opts);
+
+typedef struct dmt_server dmt_server;
+
+/* Starts a server on HIP device hip_device: a worker thread with its own context and stream.
+ * Jobs are admitted in submission order while the summed workspace estimates of the jobs in
+ * flight stay within hbm_budget_bytes (a job always starts on an idle server) and at most
+ * max_jobs (1..4096) are in flight.  Admitted jobs are set up and then advance together in
+ * rounds of one loop launch (at most 512 iterations per job), so later jobs join at the next
+ * round and finished ones leave after theirs.  Each job's results equal those of dmt_correct. */
+dmt_status dmt_server_create(dmt_server **srv, int hip_device, int64_t hbm_budget_bytes, int32_t max_jobs);
+
+/* Waits for every submitted job to finish, then stops the worker and frees the server. */
+dmt_status dmt_server_destroy(dmt_server *srv);
+
+/* Queues one job (the descriptor is copied; flags must be 0).  Its device buffers must hold the
+ * inputs when this is called (the server works on its own stream) and stay valid, untouched by
+ * the caller, until dmt_server_poll returns DMT_OK for the ticket.  Invalid descriptors are
+ * rejected here with DMT_E_INVALID.  Thread-safe. */
+dmt_status dmt_server_submit(dmt_server *srv, const dmt_job *job, int64_t *ticket);
+
+/* Result of a ticket: DMT_OK once the job has finished (result gets the descriptor with status
+ * and stats filled; the ticket is then released), DMT_W_PENDING while it runs (wait = 0) or
+ * after waiting for it (wait != 0, never returns pending), DMT_E_INVALID for an unknown ticket.
+ * The lossless edits are the vertices with q_out == 0xFF, with values g_out.  Thread-safe. */
+dmt_status dmt_server_poll(dmt_server *srv, int64_t ticket, int32_t wait, dmt_job *result);
 
 /* Lossless edits of the last dmt_correct: vertex ids ascending and their final values.
  * Writes min(count, cap) entries, returns the full count in count_host. */

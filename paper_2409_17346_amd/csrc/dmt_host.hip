@@ -12,6 +12,11 @@
 #include <cstring>
 #include <string>
 #include <vector>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
 
 #include "dmt.h"
 #include "dmt_frontier.h"
@@ -339,6 +344,7 @@ struct Job {
     float* g_out = nullptr;
     uint8_t* q_out = nullptr;
     JobWs* w = nullptr;
+    int slot = 0;           // index of the job's control block in ctl_all (and hctl)
     FrontierBufs B{};
     dmt_stats stats{};
     dmt_status status = DMT_OK;
@@ -541,7 +547,8 @@ dmt_status grid_iterations(dmt_context* c, const FrontierBufs& B, const Dims& dm
 // workgroup per job at a time.  A single job may keep a log; its loop pauses when the log is
 // full and is launched again after the log has grown.  Every launch ends after a bounded
 // number of iterations.
-dmt_status run_wg(dmt_context* c, std::vector<Job*>& jobs, bool with_log, hipStream_t st) {
+dmt_status run_wg(dmt_context* c, std::vector<Job*>& jobs, bool with_log, hipStream_t st, int max_launches = -1,
+                  int max_passes = 1 << 18) {
     const int nj = (int)jobs.size();
     int ncu = 0, occ2 = 0, occ3 = 0;
     HIPCHK(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device));
@@ -574,7 +581,6 @@ dmt_status run_wg(dmt_context* c, std::vector<Job*>& jobs, bool with_log, hipStr
         bound = b > bound ? b : bound;
     }
     HIPCHK(c, hipMemcpyAsync(c->jobs_dev.p, hb.data(), sizeof(FrontierBufs) * nj, hipMemcpyHostToDevice, st));
-    const int max_passes = 1 << 18;
     // iterations with more than `big` affected and listed anchors are handed to full-grid
     // launches (a workgroup takes about 1 us per 100 such anchors, the grid far less); the loop
     // kernel ends once every job has finished or paused, then the host runs a few iterations of
@@ -588,7 +594,7 @@ dmt_status run_wg(dmt_context* c, std::vector<Job*>& jobs, bool with_log, hipStr
     int grid_batch = nj == 1 ? 4 : 64;
     if (const char* e = getenv("DMT_GRID_BATCH")) grid_batch = atoi(e) > 0 ? atoi(e) : grid_batch;
     int64_t progress = -1;
-    for (;;) {
+    for (int launch = 0; max_launches < 0 || launch < max_launches; launch++) {
         HIPCHK(c, hipMemsetAsync(c->queue.p, 0, sizeof(int) * 2, st));
         {
             ProfScope ps(c, DMT_PROF_LOOP, st, 0);
@@ -623,12 +629,13 @@ dmt_status run_wg(dmt_context* c, std::vector<Job*>& jobs, bool with_log, hipStr
                 HIPCHK(c, hipStreamWaitEvent(st, c->join, 0));
             }
         }
-        HIPCHK(c, hipMemcpyAsync(c->hctl.data(), c->ctl_all.p, sizeof(Ctl) * nj, hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipMemcpyAsync(c->hctl.data(), c->ctl_all.p, sizeof(Ctl) * c->hctl.size(), hipMemcpyDeviceToHost,
+                                 st));
         HIPCHK(c, hipStreamSynchronize(st));
         bool running = false, log_full = false;
         int64_t max_it = 0, sum_it = 0;
         for (int j = 0; j < nj; j++) {
-            const Ctl& h = c->hctl[j];
+            const Ctl& h = c->hctl[jobs[j]->slot];
             sum_it += h.it + (h.done != 0);
             if (h.done) continue;
             running = true;
@@ -641,12 +648,12 @@ dmt_status run_wg(dmt_context* c, std::vector<Job*>& jobs, bool with_log, hipStr
         progress = sum_it;
         bool any_paused = false;
         for (int j = 0; j < nj; j++) {
-            if (c->hctl[j].done || !c->hctl[j].paused) continue;
+            if (c->hctl[jobs[j]->slot].done || !c->hctl[jobs[j]->slot].paused) continue;
             // a large iteration: run a few as full-grid launches, with room in the log for them
             any_paused = true;
             const Job* J = jobs[j];
             FrontierBufs& hj = hb[pos[j]];
-            const int64_t it0 = c->hctl[j].it;
+            const int64_t it0 = c->hctl[jobs[j]->slot].it;
             if (with_log && it0 + grid_batch + 2 > hj.log_cap) {
                 TRY(grow_log(c, (size_t)(it0 + grid_batch) * 2 + 4096, it0, st));
                 hj.log = P<long long>(c->dlog);
@@ -662,7 +669,7 @@ dmt_status run_wg(dmt_context* c, std::vector<Job*>& jobs, bool with_log, hipStr
         if (any_paused) continue;
         if (!log_full) continue;
         // the log is full (a single job): grow it, point the job at it and resume
-        const int64_t host_it = c->hctl[0].it;
+        const int64_t host_it = c->hctl[jobs[0]->slot].it;
         TRY(grow_log(c, (size_t)host_it * 2 + 4096, host_it, st));
         hb[0].log = P<long long>(c->dlog);
         hb[0].log_cap = (int)(c->dlog.cap / (sizeof(long long) * DMT_LOG_WORDS));
@@ -862,6 +869,7 @@ dmt_status run_jobs(dmt_context* c, std::vector<Job>& jobs, bool single, hipStre
     // a2 and frontier state for every live job (control blocks side by side), then the loop
     ENSURE(c, c->ctl_all, sizeof(Ctl) * live.size());
     for (size_t k = 0; k < live.size(); k++) {
+        live[k]->slot = (int)k;
         Ctl* ctl = P<Ctl>(c->ctl_all) + k;
         TRY(live[k]->D == 2 ? job_frontier<2>(c, *live[k], ctl, st) : job_frontier<3>(c, *live[k], ctl, st));
     }
@@ -892,6 +900,143 @@ dmt_status run_jobs(dmt_context* c, std::vector<Job>& jobs, bool single, hipStre
 
 // ==========================================================================================
 // C ABI
+
+
+// ==========================================================================================
+// Served form: a worker thread owns a context and a stream; jobs are admitted while their
+// estimated workspace fits the HBM budget, set up, and then advance together in rounds of one
+// loop launch (at most ROUND_PASSES iterations per job), so jobs submitted later join the next
+// round and finished ones leave after it (continuous batching).
+
+namespace {
+
+constexpr int ROUND_PASSES = 512;
+
+int64_t workspace_estimate(int D, int64_t n) {
+    // fields, state, f and g planes, frontier lists and stamps, separatrix branches (an upper
+    // estimate of what the correction of one field allocates; the branches are data-dependent)
+    return (D == 2 ? 112 : 224) * n + (1 << 20);
+}
+
+struct Ticket {
+    dmt_job job{};
+    Job J;
+    int64_t bytes = 0;
+    int state = 0;          // 0 pending, 1 active, 2 done
+};
+
+}  // namespace
+
+struct dmt_server {
+    dmt_context* c = nullptr;
+    hipStream_t st = nullptr;
+    int64_t budget = 0;
+    int max_jobs = 0;
+    std::thread worker;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    bool stop = false;
+    std::unordered_map<int64_t, Ticket> tickets;
+    std::deque<int64_t> pending;
+    std::vector<int> free_slots;
+    int64_t next_ticket = 1;
+    int64_t inflight = 0;
+};
+
+namespace {
+
+void server_finish(dmt_server* s, Ticket& t, dmt_status status) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    t.job.status = status;
+    t.job.stats = t.J.stats;
+    t.state = 2;
+    s->inflight -= t.bytes;
+    s->free_slots.push_back(t.J.slot);
+    s->cv_done.notify_all();
+}
+
+// Setup, f's gradient and branches, frontier state and iteration 0 of newly admitted jobs.
+dmt_status server_admit(dmt_server* s, std::vector<Ticket*>& admit, std::vector<Ticket*>& active) {
+    dmt_context* c = s->c;
+    const hipStream_t st = s->st;
+    HIPCHK(c, hipMemsetAsync(c->flags.p, 0, sizeof(unsigned) * (s->max_jobs + 1), st));
+    for (Ticket* t : admit) {
+        Job& J = t->J;
+        J.w = &c->ws[J.slot];
+        unsigned* flag = P<unsigned>(c->flags) + 1 + J.slot;
+        TRY(J.D == 2 ? job_setup<2>(c, J, flag, st) : job_setup<3>(c, J, flag, st));
+    }
+    std::vector<unsigned> fl(s->max_jobs + 1);
+    HIPCHK(c, hipMemcpyAsync(fl.data(), c->flags.p, sizeof(unsigned) * fl.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    for (Ticket* t : admit) {
+        Job& J = t->J;
+        const unsigned f = fl[1 + J.slot];
+        if (f & 1u) { server_finish(s, *t, DMT_E_NONFINITE); continue; }
+        if (f & 2u) { server_finish(s, *t, DMT_E_BOUND); continue; }
+        Ctl* ctl = P<Ctl>(c->ctl_all) + J.slot;
+        TRY(J.D == 2 ? job_frontier<2>(c, J, ctl, st) : job_frontier<3>(c, J, ctl, st));
+        TRY(J.D == 2 ? job_iteration0<2>(c, J, st) : job_iteration0<3>(c, J, st));
+        active.push_back(t);
+    }
+    return DMT_OK;
+}
+
+// One round of the active jobs; finished ones get their outputs and leave.
+dmt_status server_round(dmt_server* s, std::vector<Ticket*>& active) {
+    dmt_context* c = s->c;
+    std::vector<Job*> js;
+    for (Ticket* t : active) js.push_back(&t->J);
+    TRY(run_wg(c, js, false, s->st, 1, ROUND_PASSES));
+    std::vector<Ticket*> still;
+    for (Ticket* t : active) {
+        const Ctl h = c->hctl[t->J.slot];
+        if (!h.done) {
+            still.push_back(t);
+            continue;
+        }
+        TRY(job_outputs(c, t->J, h, false, s->st));
+        server_finish(s, *t, t->J.status);
+    }
+    active.swap(still);
+    return DMT_OK;
+}
+
+void server_main(dmt_server* s) {
+    (void)hipSetDevice(s->c->device);
+    std::vector<Ticket*> active;
+    for (;;) {
+        std::vector<Ticket*> admit;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv_work.wait(lk, [&] { return s->stop || !s->pending.empty() || !active.empty(); });
+            if (s->stop && s->pending.empty() && active.empty()) break;
+            // admission by footprint: the first job always fits an idle server
+            while (!s->pending.empty() && !s->free_slots.empty()) {
+                Ticket& t = s->tickets.at(s->pending.front());
+                if ((!active.empty() || !admit.empty()) && s->inflight + t.bytes > s->budget) break;
+                s->inflight += t.bytes;
+                t.J.slot = s->free_slots.back();
+                s->free_slots.pop_back();
+                t.state = 1;
+                admit.push_back(&t);
+                s->pending.pop_front();
+            }
+        }
+        dmt_status rc = DMT_OK;
+        if (!admit.empty()) rc = server_admit(s, admit, active);
+        if (rc == DMT_OK && !active.empty()) rc = server_round(s, active);
+        if (rc != DMT_OK) {
+            // a HIP failure ends every job in flight with that status
+            for (Ticket* t : active) server_finish(s, *t, rc);
+            for (Ticket* t : admit)
+                if (t->state == 1) server_finish(s, *t, rc);
+            active.clear();
+        }
+    }
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -1200,6 +1345,97 @@ dmt_status dmt_apply_edits(dmt_context* c, const float* g_hat, const uint8_t* q,
     HIPCHK(c, hipMemcpyAsync(c->hscratch, c->flags.p, sizeof(unsigned), hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));
     if (*reinterpret_cast<unsigned*>(c->hscratch)) return fail(c, DMT_E_INVALID, "lossless index out of range");
+    return DMT_OK;
+}
+
+
+int64_t dmt_workspace_bytes(const dmt_grid* gr, const dmt_options* o) {
+    if (!gr || !o) return -1;
+    Dims dm;
+    int D;
+    if (check_grid(nullptr, gr, dm, D) != DMT_OK) return -1;
+    return workspace_estimate(D, dm.n);
+}
+
+dmt_status dmt_server_create(dmt_server** out, int hip_device, int64_t hbm_budget_bytes, int32_t max_jobs) {
+    if (!out || hbm_budget_bytes <= 0 || max_jobs < 1 || max_jobs > 4096) return DMT_E_INVALID;
+    *out = nullptr;
+    dmt_server* s = new dmt_server();
+    dmt_status rc = dmt_context_create(&s->c, hip_device);
+    if (rc != DMT_OK) {
+        delete s;
+        return rc;
+    }
+    dmt_context* c = s->c;
+    s->budget = hbm_budget_bytes;
+    s->max_jobs = max_jobs;
+    c->ws.resize(max_jobs);
+    c->hctl.assign(max_jobs, Ctl{});
+    if (hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking) != hipSuccess ||
+        ensure(c, c->ctl_all, sizeof(Ctl) * max_jobs) != DMT_OK ||
+        ensure(c, c->flags, sizeof(unsigned) * (max_jobs + 1)) != DMT_OK ||
+        hipMemsetAsync(c->ctl_all.p, 0, sizeof(Ctl) * max_jobs, s->st) != hipSuccess) {
+        if (s->st) (void)hipStreamDestroy(s->st);
+        dmt_context_destroy(c);
+        delete s;
+        return DMT_E_NOMEM;
+    }
+    for (int k = max_jobs - 1; k >= 0; k--) s->free_slots.push_back(k);
+    s->worker = std::thread(server_main, s);
+    *out = s;
+    return DMT_OK;
+}
+
+dmt_status dmt_server_destroy(dmt_server* s) {
+    if (!s) return DMT_OK;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+    }
+    s->cv_work.notify_all();
+    if (s->worker.joinable()) s->worker.join();
+    (void)hipSetDevice(s->c->device);
+    if (s->st) (void)hipStreamDestroy(s->st);
+    dmt_context_destroy(s->c);
+    delete s;
+    return DMT_OK;
+}
+
+dmt_status dmt_server_submit(dmt_server* s, const dmt_job* job, int64_t* ticket) {
+    if (!s || !job || !ticket) return DMT_E_INVALID;
+    Ticket t;
+    t.job = *job;
+    t.job.stats = dmt_stats{};
+    Job& J = t.J;
+    dmt_status rc = check_grid(nullptr, &job->grid, J.dm, J.D);
+    if (rc == DMT_OK) rc = check_options(nullptr, &job->opts, job->xi);
+    if (rc == DMT_OK && job->opts.flags != 0) rc = DMT_E_INVALID;
+    if (rc == DMT_OK && (!job->f || !job->g_hat || !job->g_out || !job->q_out)) rc = DMT_E_INVALID;
+    if (rc != DMT_OK) return rc;
+    J.f = job->f; J.gh = job->g_hat; J.xi = job->xi; J.o = job->opts; J.g_out = job->g_out; J.q_out = job->q_out;
+    t.bytes = workspace_estimate(J.D, J.dm.n);
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->stop) return DMT_E_INVALID;
+        *ticket = s->next_ticket++;
+        s->tickets.emplace(*ticket, std::move(t));
+        s->pending.push_back(*ticket);
+    }
+    s->cv_work.notify_all();
+    return DMT_OK;
+}
+
+dmt_status dmt_server_poll(dmt_server* s, int64_t ticket, int32_t wait, dmt_job* result) {
+    if (!s || !result) return DMT_E_INVALID;
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->tickets.find(ticket);
+    if (it == s->tickets.end()) return DMT_E_INVALID;
+    if (it->second.state != 2) {
+        if (!wait) return DMT_W_PENDING;
+        s->cv_done.wait(lk, [&] { return it->second.state == 2; });
+    }
+    *result = it->second.job;
+    s->tickets.erase(it);
     return DMT_OK;
 }
 

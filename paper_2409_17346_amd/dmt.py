@@ -11,7 +11,7 @@ from __future__ import annotations
 import ctypes as C
 import os
 from dataclasses import dataclass
-from typing import Dict, Tuple
+from typing import Dict, Optional, Tuple
 
 import torch
 
@@ -20,8 +20,9 @@ SO = os.path.join(HERE, "libdmt.so")
 
 DMT_OK = 0
 DMT_W_NOT_CONVERGED = 1
-STATUS_NAMES = {0: "ok", 1: "not_converged", -1: "invalid", -2: "bound", -3: "nonfinite", -4: "nomem",
-                -5: "hip"}
+DMT_W_PENDING = 2
+STATUS_NAMES = {0: "ok", 1: "not_converged", 2: "pending", -1: "invalid", -2: "bound", -3: "nonfinite",
+                -4: "nomem", -5: "hip"}
 LOG_WORDS = 20
 LOG_KEYS = ["kind", "FP0", "FN0", "FP1", "FN1", "FP2", "FN2", "FP3", "FN3", "TM_desc", "TM_asc", "n_req",
             "changed", "dirty_vertices", "affected_anchors", "listed_anchors", "branches_settled",
@@ -39,7 +40,8 @@ ABI_SYMBOLS = [
     "dmt_context_create", "dmt_context_destroy", "dmt_last_error", "dmt_cell_id_space",
     "dmt_xi_from_relative", "dmt_bounds", "dmt_gradient_pairs", "dmt_extract_msc", "dmt_msc_copy",
     "dmt_correct", "dmt_correct_batch", "dmt_lossless_edits", "dmt_iteration_log", "dmt_apply_edits",
-    "dmt_profile_enable", "dmt_profile_read",
+    "dmt_profile_enable", "dmt_profile_read", "dmt_workspace_bytes", "dmt_server_create", "dmt_server_destroy",
+    "dmt_server_submit", "dmt_server_poll",
 ]
 
 PROF_KERNELS = {"gradient": 0, "classify": 1, "apply": 2, "sstep": 3, "setup": 4, "msc": 5, "loop": 6,
@@ -106,9 +108,15 @@ def load_library(path: str = SO):
     L.dmt_apply_edits.argtypes = [VP, VP, VP, C.c_int64, VP, VP, C.c_int64, C.c_float, C.c_int32, VP, VP]
     L.dmt_profile_enable.argtypes = [VP, C.c_int]
     L.dmt_profile_read.argtypes = [VP, C.c_int, P64, C.POINTER(C.c_double), P64]
+    L.dmt_workspace_bytes.argtypes = [C.POINTER(dmt_grid), C.POINTER(dmt_options)]
+    L.dmt_server_create.argtypes = [C.POINTER(VP), C.c_int, C.c_int64, C.c_int32]
+    L.dmt_server_destroy.argtypes = [VP]
+    L.dmt_server_submit.argtypes = [VP, C.POINTER(dmt_job), P64]
+    L.dmt_server_poll.argtypes = [VP, C.c_int64, C.c_int32, C.POINTER(dmt_job)]
     for name in ABI_SYMBOLS:
         if name != "dmt_last_error":
             getattr(L, name).restype = C.c_int
+    L.dmt_workspace_bytes.restype = C.c_int64
     _lib = L
     return L
 
@@ -343,3 +351,71 @@ def dmt_profile_read(ctx: Context) -> Dict[str, Dict[str, float]]:
         ctx.check(ctx.L.dmt_profile_read(ctx.h, k, C.byref(n), C.byref(ms), C.byref(u)))
         out[name] = {"launches": int(n.value), "ms": float(ms.value), "units": int(u.value)}
     return out
+
+
+def dmt_workspace_bytes(shape, tier: int = 4, q_max: int = 6) -> int:
+    L = load_library()
+    g = dmt_grid(2, shape[1], shape[0], 1) if len(shape) == 2 else dmt_grid(3, shape[2], shape[1], shape[0])
+    return int(L.dmt_workspace_bytes(C.byref(g), C.byref(dmt_options(tier, q_max, -1, 0))))
+
+
+class Server:
+    """The served form: dmt_server_create / submit / poll / destroy.  Inputs must be complete on
+    the device when submitted (the server runs on its own stream); keep the tensors alive until
+    the ticket is polled."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 64 << 30, max_jobs: int = 64):
+        self.L = load_library()
+        h = VP()
+        st = self.L.dmt_server_create(C.byref(h), device, hbm_budget_bytes, max_jobs)
+        if st != DMT_OK:
+            raise DmtError(st, "dmt_server_create failed")
+        self.h = h
+        self._held = {}
+
+    def submit(self, f: torch.Tensor, g_hat: torch.Tensor, xi: float, tier: int = 4, q_max: int = 6,
+               max_iters: int = -1, g_out: Optional[torch.Tensor] = None, q_out: Optional[torch.Tensor] = None) -> int:
+        _dev(f)
+        _dev(g_hat)
+        if g_out is None:
+            g_out = torch.empty_like(f)
+        if q_out is None:
+            q_out = torch.empty(f.shape, dtype=torch.uint8, device=f.device)
+        j = dmt_job()
+        j.grid = grid_of(f)
+        j.f, j.g_hat, j.xi = f.data_ptr(), g_hat.data_ptr(), xi
+        j.opts = dmt_options(tier, q_max, max_iters, 0)
+        j.g_out, j.q_out = g_out.data_ptr(), q_out.data_ptr()
+        torch.cuda.current_stream(f.device).synchronize()   # inputs complete before the server reads them
+        t = C.c_int64()
+        st = self.L.dmt_server_submit(self.h, C.byref(j), C.byref(t))
+        if st != DMT_OK:
+            raise DmtError(st, "dmt_server_submit rejected the job")
+        self._held[t.value] = (f, g_hat, g_out, q_out)
+        return t.value
+
+    def poll(self, ticket: int, wait: bool = False) -> Optional[Result]:
+        """Result of a finished ticket (then released), or None while it runs."""
+        j = dmt_job()
+        st = self.L.dmt_server_poll(self.h, ticket, 1 if wait else 0, C.byref(j))
+        if st == DMT_W_PENDING:
+            return None
+        if st != DMT_OK:
+            raise DmtError(st, "unknown ticket")
+        f, gh, g_out, q_out = self._held.pop(ticket)
+        stj = int(j.status)
+        idx = torch.nonzero(q_out.reshape(-1) == 0xFF).reshape(-1) if stj >= 0 else None
+        val = g_out.reshape(-1)[idx] if stj >= 0 else None
+        return Result(STATUS_NAMES.get(stj, str(stj)), g_out, q_out, j.stats.as_dict(), idx, val, None)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.dmt_server_destroy(self.h)
+            self.h = None
+            self._held.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

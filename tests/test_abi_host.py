@@ -10,7 +10,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _declared():
     src = open(os.path.join(ROOT, "include", "dmt.h")).read()
-    return sorted(set(re.findall(r"^\s*(?:dmt_status|const char \*)\s*(dmt_\w+)\s*\(", src, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:dmt_status|const char \*|int64_t)\s*(dmt_\w+)\s*\(", src, re.M)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -40,3 +40,10 @@ def test_binding_refuses_cpu_tensors():
     from paper_2409_17346_amd import dmt
     with pytest.raises(ValueError):
         dmt._dev(torch.zeros(4, 4))
+
+
+def test_workspace_estimate():
+    from paper_2409_17346_amd import dmt
+    assert dmt.dmt_workspace_bytes((128, 128)) == 112 * 128 * 128 + (1 << 20)
+    assert dmt.dmt_workspace_bytes((8, 9, 10)) == 224 * 720 + (1 << 20)
+    assert dmt.dmt_workspace_bytes((1, 9)) == -1

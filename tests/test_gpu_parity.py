@@ -280,3 +280,81 @@ def test_correct_batch_isolates_bad_jobs(ctx, dmt):
     for r in (res[0], res[2]):
         assert r.status == o["status"]
         assert np.array_equal(r.g.cpu().numpy().reshape(-1).view(np.uint32), o["g"].view(np.uint32))
+
+
+# ------------------------------------------------------------------------------------------
+# Served form: every job of a request stream equals the oracle
+
+def _server_jobs():
+    ws = [synth.tiny_cases(50 + i, shape, rel=rel, kind=kind, ghat=ghat)
+          for i, (shape, kind, ghat, rel) in enumerate(CORR_CASES)]
+    ws.append(synth.config_small2d())
+    ws.append(synth.config_atoms3d(seed=7, side=20, n_atoms=6))
+    return ws
+
+
+def _check_against_oracle(w, r):
+    nx, ny, nz = w.dims
+    o = oracle.correct(oracle.Complex.grid(nx, ny, nz), w.f.reshape(-1), w.g_hat.reshape(-1), w.xi, 4, 6)
+    assert r.status == o["status"], w.name
+    for k, v in o["stats"].items():
+        if k != "status":
+            assert r.stats[k] == v, (w.name, k)
+    assert np.array_equal(r.g.cpu().numpy().reshape(-1).view(np.uint32), o["g"].view(np.uint32)), w.name
+    assert np.array_equal(r.q.cpu().numpy().reshape(-1), o["q"]), w.name
+    assert np.array_equal(r.lossless_idx.cpu().numpy(), o["lossless_idx"]), w.name
+
+
+@pytest.mark.parametrize("budget,max_jobs", [(64 << 30, 64), (1, 64), (64 << 30, 2)])
+def test_server_matches_oracle(dmt, budget, max_jobs):
+    """All jobs submitted at once; with a 1-byte budget the server admits one job at a time, with
+    max_jobs 2 two at a time."""
+    ws = _server_jobs()
+    srv = dmt.Server(0, hbm_budget_bytes=budget, max_jobs=max_jobs)
+    try:
+        tickets = [srv.submit(_t(w.f), _t(w.g_hat), w.xi) for w in ws]
+        for w, t in zip(ws, tickets):
+            _check_against_oracle(w, srv.poll(t, wait=True))
+    finally:
+        srv.close()
+
+
+def test_server_continuous_arrivals(ctx, dmt):
+    """Jobs arrive while others run (non-blocking polls in between); each equals dmt_correct."""
+    ws = _server_jobs()
+    srv = dmt.Server(0, max_jobs=4)
+    try:
+        live, done = {}, {}
+        for i, w in enumerate(ws):
+            live[srv.submit(_t(w.f), _t(w.g_hat), w.xi)] = i
+            for t in list(live):
+                r = srv.poll(t)
+                if r is not None:
+                    done[live.pop(t)] = r
+        for t, i in live.items():
+            done[i] = srv.poll(t, wait=True)
+        for i, w in enumerate(ws):
+            s = dmt.dmt_correct(ctx, _t(w.f), _t(w.g_hat), w.xi, 4, 6)
+            assert done[i].status == s.status and done[i].stats == s.stats, w.name
+            assert torch.equal(done[i].g.view(torch.int32), s.g.view(torch.int32)) and torch.equal(done[i].q, s.q)
+    finally:
+        srv.close()
+
+
+def test_server_errors(dmt):
+    w = synth.tiny_cases(5, (10, 12), rel=0.1, kind="uniform")
+    srv = dmt.Server(0)
+    try:
+        f = _t(w.f)
+        with pytest.raises(dmt.DmtError):
+            srv.submit(f[:1], f[:1], w.xi)                  # grid too small
+        with pytest.raises(dmt.DmtError):
+            srv.submit(f, f, w.xi, tier=9)                  # bad tier
+        t_bad = srv.submit(f, f + 1.0, w.xi)                # |g_hat - f| > xi
+        t_ok = srv.submit(f, _t(w.g_hat), w.xi)
+        assert srv.poll(t_bad, wait=True).status == "bound"
+        _check_against_oracle(w, srv.poll(t_ok, wait=True))
+        with pytest.raises(dmt.DmtError):
+            srv.poll(t_ok)                                  # released
+    finally:
+        srv.close()
