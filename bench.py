@@ -163,12 +163,74 @@ def bench_batch(args):
     ctx.close()
 
 
+def bench_served(args):
+    """The served form: a Poisson stream of correction requests into dmt_server.  Requests draw
+    their fields from a pool: 23 fields like the batch mix (2D side 256-1024, 3D side 64-160,
+    xi = 1e-4 * range) and one 384^3 lognormal 3D field used by the ~5% large requests.  Reports
+    MB/s of fields completed over the stream's wall time and p50/p99 request latency (arrival to
+    completion)."""
+    import numpy as np
+    import torch
+    from paper_2409_17346_amd import dmt, synth
+    rng = np.random.default_rng(6000)
+    big_ids = [j for j in range(args.requests) if np.random.default_rng(5000 + j).uniform() < 0.05]
+    small = [synth.served_job(j) for j in range(40) if np.random.default_rng(5000 + j).uniform() >= 0.05][:23]
+    big = synth.served_job(big_ids[0]) if big_ids else None
+    pool = [(torch.from_numpy(w.f).cuda(), torch.from_numpy(w.g_hat).cuda(), w.xi, w.f.size) for w in small]
+    bigt = (torch.from_numpy(big.f).cuda(), torch.from_numpy(big.g_hat).cuda(), big.xi, big.f.size) if big else None
+    reqs = [bigt if j in big_ids else pool[int(rng.integers(0, len(pool)))] for j in range(args.requests)]
+    arrivals = np.cumsum(rng.exponential(1.0 / args.qps, size=args.requests))
+    print(f"[bench] served: {args.requests} requests ({len(big_ids)} of 384^3) at {args.qps} req/s",
+          file=sys.stderr, flush=True)
+    srv = dmt.Server(0, hbm_budget_bytes=96 << 30, max_jobs=64)
+    # warmup: one request of each pool field kind
+    for r in reqs[:args.warmup]:
+        srv.poll(srv.submit(r[0], r[1], r[2]), wait=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nxt, live, lat, status, done_bytes = 0, {}, [], {}, 0.0
+    t_last = t0
+    while nxt < len(reqs) or live:
+        now = time.perf_counter() - t0
+        while nxt < len(reqs) and arrivals[nxt] <= now:
+            f, g, xi, n = reqs[nxt]
+            live[srv.submit(f, g, xi)] = (arrivals[nxt], n)
+            nxt += 1
+        for t in list(live):
+            res = srv.poll(t)
+            if res is not None:
+                a, n = live.pop(t)
+                t_last = time.perf_counter()
+                lat.append(t_last - t0 - a)
+                done_bytes += 4.0 * n
+                status[res.status] = status.get(res.status, 0) + 1
+                if len(lat) % 20 == 0:
+                    print(f"[bench] {len(lat)} done, latency p50 {np.percentile(lat, 50):.3f} s", file=sys.stderr,
+                          flush=True)
+        time.sleep(0.0005)
+    elapsed = t_last - t0
+    srv.close()
+    lat_ms = np.array(lat) * 1e3
+    line = {
+        "metric": METRIC, "value": round(done_bytes / elapsed / 1e6, 3), "unit": "MB/s", "n_gpus": 1,
+        "steps": len(lat), "warmup": args.warmup, "ms_per_step": round(elapsed / len(lat) * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"served-poisson-{args.qps}qps-{args.requests}req", "big_requests": len(big_ids),
+                   "tier": 4, "q_max": 6, "status": status},
+        "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 3),
+                       "p99": round(float(np.percentile(lat_ms, 99)), 3)},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="large2d", choices=["large2d", "small2d", "atoms3d", "batch64"])
+    ap.add_argument("--workload", default="large2d", choices=["large2d", "small2d", "atoms3d", "batch64", "served"])
+    ap.add_argument("--requests", type=int, default=200, help="served: requests in the stream")
+    ap.add_argument("--qps", type=float, default=4.0, help="served: Poisson arrival rate (requests/s)")
     ap.add_argument("--cpu-crop", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--flags", type=int, default=0, help="dmt_options.flags (1 dense loop, 2 one launch per phase)")
@@ -188,6 +250,8 @@ def main():
         raise SystemExit("bench.py needs a GPU")
     if args.workload == "batch64":
         return bench_batch(args)
+    if args.workload == "served":
+        return bench_served(args)
     if args.copy_probe_mib > 0:
         src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
