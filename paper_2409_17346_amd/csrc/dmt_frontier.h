@@ -690,20 +690,21 @@ __device__ __forceinline__ void record_iteration(const FrontierView& B, int it, 
     if (cstep) c->c_it++; else c->s_it++;
 }
 
-// Every branch starts as a candidate (list 0).
+// The first candidate list (list 0): the branches whose first differing cell the dense scan of
+// iteration 0 set.  ctl->n_cand[0] must be 0 before the launch.
 __global__ void __launch_bounds__(256) k_fr_cand_init(FrontierBufs hb, Ctl* c) {
     const FrontierView& B = view(hb);
     const int nb = B.n_desc + B.n_asc;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i0 = i - (int)(threadIdx.x & 63u);
+    if (i0 >= nb) return;
+    bool set = false;
     if (i < nb) {
-        B.cand[0][i] = i;
-        B.inlist[i] = 1;
+        set = (i < B.n_desc ? B.dfirst[i] : B.afirst[i - B.n_desc]) != INF32;
+        B.inlist[i] = set;
     }
-    if (i == 0) {
-        c->cand_sel = 0;
-        c->n_cand[0] = nb;
-        c->n_cand[1] = 0;
-    }
+    const int idx = wave_append(set, &c->n_cand[0]);
+    if (set) B.cand[0][idx] = i;
 }
 
 __global__ void k_fr_init(Ctl* c) {
@@ -776,9 +777,10 @@ __device__ __forceinline__ int wave_decide(const FrontierView& B, int it, int la
 // The loop of one job from the end of its iteration ctl->it's violation pass (the
 // precondition: that iteration's gradient, violation and branch passes are done), in one
 // workgroup, synchronised by workgroup barriers only.  Returns when the job ends, when its log
-// is full, after max_passes iterations, or (big > 0) before an iteration with more than big
-// affected and listed anchors, with ctl->paused set and ctl->it that iteration, whose passes
-// have not started; the host runs such iterations as full-grid launches.
+// is full, after max_passes iterations, or (big > 0) before a large step: ctl->paused = 1 before
+// an iteration with more than big affected and listed anchors (ctl->it that iteration, whose
+// passes have not started), ctl->paused = 2 before a troublemaker pass over more than big
+// candidates (ctl->it the iteration it belongs to); the host runs those as full-grid launches.
 template <int D>
 __device__ __forceinline__ void run_job_wg(const FrontierView& B, int max_passes, int big) {
     const Dims dm = B.dm;
@@ -799,9 +801,16 @@ __device__ __forceinline__ void run_job_wg(const FrontierView& B, int max_passes
         if (B.log && it >= B.log_cap) break;
         if (tid < 64) {
             const bool s_step = B.tier >= 3 && c_total(slot_of(B, it)) == 0;
-            if (tid == 0) sstep_sh = s_step;
+            int act = s_step;
+            // a troublemaker pass over more than `big` candidates is left to the grid too
+            if (s_step && big > 0 && ld_relaxed(&c->n_cand[ld_relaxed(&c->cand_sel)]) > big) {
+                if (tid == 0) c->paused = 2;
+                act = 2;
+            }
+            if (tid == 0) sstep_sh = act;
         }
         __syncthreads();
+        if (sstep_sh == 2) break;
         if (sstep_sh) {
             phase_sapply<D>(B, dm, it, (long long)it != B.max_iters, tid, nt);
             __syncthreads();

@@ -70,7 +70,7 @@ struct dmt_context {
     std::string err;
     std::vector<JobWs> ws;                 // one workspace per job of the last batch (ws[0]: single calls)
     MscBufs msc;                           // results of dmt_extract_msc
-    DevBuf gpl, req, cnt, flags, part, blk, blkoff, ll_idx, ll_val, dlog, jobs_dev, ctl_all, queue;
+    DevBuf gpl, req, cnt, flags, part, blk, blkoff, ll_idx, ll_val, dlog, jobs_dev, ctl_all, queue, scan_tsum, scan_toff;
     int64_t n_lossless = 0;
     std::vector<int64_t> log;
     unsigned long long* hcnt = nullptr;    // pinned
@@ -204,7 +204,17 @@ dmt_status launch_grad(dmt_context* c, int D, const float* h, uint8_t* pl, const
 
 // exclusive scan of n ints into n+1 int64 (device); the total is returned on the host
 dmt_status scan(dmt_context* c, const int* in, int64_t n, int64_t* out, int64_t* total, hipStream_t st) {
-    k_scan_single<<<1, 1024, 0, st>>>(in, n, out);
+    if (n <= 65536) {
+        k_scan_single<<<1, 1024, 0, st>>>(in, n, out);
+    } else {
+        // tiles of 1024: tile sums, a single-block scan of the sums, then each tile's prefix
+        const int64_t ntiles = (n + 1023) / 1024;
+        ENSURE(c, c->scan_tsum, sizeof(int) * (size_t)ntiles);
+        ENSURE(c, c->scan_toff, sizeof(int64_t) * (size_t)(ntiles + 1));
+        k_tile_sum<<<(unsigned)ntiles, TPB, 0, st>>>(in, (int)n, P<int>(c->scan_tsum));
+        k_scan_single<<<1, 1024, 0, st>>>(P<int>(c->scan_tsum), ntiles, P<int64_t>(c->scan_toff));
+        k_tile_scan64<<<(unsigned)ntiles, TPB, 0, st>>>(in, (int)n, P<int64_t>(c->scan_toff), out);
+    }
     CHECK_LAUNCH(c);
     if (total) {
         HIPCHK(c, hipMemcpyAsync(c->hscratch, out + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
@@ -479,10 +489,6 @@ dmt_status job_frontier(dmt_context* c, Job& J, Ctl* ctl, hipStream_t st) {
         B.cand[0] = P<int>(w.cand0);
         B.cand[1] = P<int>(w.cand1);
         B.inlist = P<uint8_t>(w.inlist);
-        if (nbr) {
-            k_fr_cand_init<<<nblocks(nbr), TPB, 0, st>>>(B, ctl);
-            CHECK_LAUNCH(c);
-        }
     }
     B.delta = ldexpf(J.xi, -J.o.q_max);
     B.q_max = J.o.q_max;
@@ -503,6 +509,8 @@ dmt_status job_iteration0(dmt_context* c, Job& J, hipStream_t st) {
     }
     ProfScope ps(c, DMT_PROF_CLASSIFY, st, n);
     k_fr_vr<D><<<gfull, TPB, 0, st>>>(J.B, J.dm);
+    const int64_t nbr = (int64_t)J.B.n_desc + J.B.n_asc;
+    if (nbr) k_fr_cand_init<<<nblocks(nbr), TPB, 0, st>>>(J.B, J.B.ctl);
     CHECK_LAUNCH(c);
     return DMT_OK;
 }
@@ -526,11 +534,18 @@ dmt_status grow_log(dmt_context* c, size_t need, int64_t keep, hipStream_t st) {
 }
 
 // K iterations of one job as full-grid launches (one per phase) from the start of iteration
-// ctl->it, then the gradient, violation and branch passes of the next one: the state the
-// resident loop starts from.  Launches of a finished job return at once.
+// ctl->it (from its troublemaker pass when from_sstep), then the gradient, violation and branch
+// passes of the next one: the state the resident loop starts from.  Launches of a finished job
+// return at once.
 template <int D>
-dmt_status grid_iterations(dmt_context* c, const FrontierBufs& B, const Dims& dm, int K, hipStream_t st) {
+dmt_status grid_iterations(dmt_context* c, const FrontierBufs& B, const Dims& dm, int K, bool from_sstep,
+                           hipStream_t st) {
     const unsigned gfull = nblocks(dm.n) < 2048u ? nblocks(dm.n) : 2048u;
+    if (from_sstep) {
+        // paused before the troublemaker pass of iteration ctl->it: finish that iteration first
+        k_fr_sapply<D><<<gfull, TPB, 0, st>>>(B, dm);
+        k_fr_finish<<<1, 1, 0, st>>>(B);
+    }
     for (int k = 0; k <= K; k++) {
         k_fr_grad<D><<<gfull, TPB, 0, st>>>(B, dm);
         k_fr_vr<D><<<gfull, TPB, 0, st>>>(B, dm);
@@ -661,10 +676,11 @@ dmt_status run_wg(dmt_context* c, std::vector<Job*>& jobs, bool with_log, hipStr
                 HIPCHK(c, hipMemcpyAsync(P<FrontierBufs>(c->jobs_dev) + pos[j], &hj, sizeof(FrontierBufs),
                                          hipMemcpyHostToDevice, st));
             }
+            const bool from_sstep = c->hctl[jobs[j]->slot].paused == 2;
             HIPCHK(c, hipMemsetAsync(&J->B.ctl->paused, 0, sizeof(int), st));
             ProfScope ps(c, DMT_PROF_LOOP, st, 0);
-            TRY(J->D == 2 ? grid_iterations<2>(c, hj, J->dm, grid_batch, st)
-                          : grid_iterations<3>(c, hj, J->dm, grid_batch, st));
+            TRY(J->D == 2 ? grid_iterations<2>(c, hj, J->dm, grid_batch, from_sstep, st)
+                          : grid_iterations<3>(c, hj, J->dm, grid_batch, from_sstep, st));
         }
         if (any_paused) continue;
         if (!log_full) continue;
@@ -684,8 +700,21 @@ dmt_status run_phases(dmt_context* c, Job& J, hipStream_t st) {
     const int n = J.dm.n;
     const unsigned gfull = nblocks(n) < 2048u ? nblocks(n) : 2048u;
     int batch = 4;
-    int64_t host_it = 0;
     Ctl h{};
+    // iteration 0 (dense passes), the first troublemaker candidates, and its decision
+    TRY(grow_log(c, (size_t)batch + 2, 0, st));
+    J.B.log = P<long long>(c->dlog);
+    {
+        ProfScope ps(c, DMT_PROF_LOOP, st, 0);
+        k_fr_grad<D><<<gfull, TPB, 0, st>>>(J.B, J.dm);
+        k_fr_vr<D><<<gfull, TPB, 0, st>>>(J.B, J.dm);
+        const int64_t nbr = (int64_t)J.B.n_desc + J.B.n_asc;
+        if (nbr) k_fr_cand_init<<<nblocks(nbr), TPB, 0, st>>>(J.B, J.B.ctl);
+        if (J.o.tier >= 3) k_fr_sapply<D><<<gfull, TPB, 0, st>>>(J.B, J.dm);
+        k_fr_finish<<<1, 1, 0, st>>>(J.B);
+        CHECK_LAUNCH(c);
+    }
+    int64_t host_it = 1;
     for (;;) {
         TRY(grow_log(c, (size_t)host_it + (size_t)batch + 1, host_it, st));
         J.B.log = P<long long>(c->dlog);
@@ -1064,7 +1093,8 @@ dmt_status dmt_context_destroy(dmt_context* c) {
     if (!c) return DMT_OK;
     (void)hipSetDevice(c->device);
     std::vector<DevBuf*> bufs = {&c->gpl, &c->req, &c->cnt, &c->flags, &c->part, &c->blk, &c->blkoff, &c->ll_idx,
-                                 &c->ll_val, &c->dlog, &c->jobs_dev, &c->ctl_all, &c->queue};
+                                 &c->ll_val, &c->dlog, &c->jobs_dev, &c->ctl_all, &c->queue, &c->scan_tsum,
+                                 &c->scan_toff};
     for (DevBuf* b : c->msc.all()) bufs.push_back(b);
     for (JobWs& w : c->ws)
         for (DevBuf* b : w.all()) bufs.push_back(b);

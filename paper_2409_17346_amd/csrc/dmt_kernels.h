@@ -572,6 +572,27 @@ __global__ void __launch_bounds__(256) k_tile_scan(int* __restrict__ in, int n, 
     if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = (int)toff[gridDim.x];
 }
 
+// The same with int64 offsets, leaving in untouched: out[i] = prefix of in at i, out[n] = total.
+__global__ void __launch_bounds__(256) k_tile_scan64(const int* __restrict__ in, int n,
+                                                     const int64_t* __restrict__ toff, int64_t* __restrict__ out) {
+    const int i0 = blockIdx.x * 1024 + threadIdx.x * 4;
+    int v[4];
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        v[k] = i0 + k < n ? in[i0 + k] : 0;
+        s += v[k];
+    }
+    int total = 0;
+    int64_t acc = toff[blockIdx.x] + block_exclusive_scan(s, total);
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        if (i0 + k < n) out[i0 + k] = acc;
+        acc += v[k];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = toff[gridDim.x];
+}
+
 // ----------------------------------------------------------------------------------------
 // MSC: critical cells (ascending ids per dimension), compacted with block scans.
 
