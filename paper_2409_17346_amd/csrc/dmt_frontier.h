@@ -205,28 +205,64 @@ __device__ __forceinline__ bool apply_vertex(const FrontierView& B, int v, int i
 
 // Marks the closed 1-ring of an edited vertex as dirty and the anchors of cells touching it as
 // affected, for iteration it + 1.  Lanes without an edit pass changed = false; whole waves
-// call it.  The stamps are claimed without branches between the atomics (a neighbour outside
-// the grid issues a maximum with 0 on the edited vertex's own entry, which changes nothing, and
-// its result is discarded), so all of them are in flight at once; the winners are then
-// appended with one atomic per list and wave.
+// call it.  Two forms, chosen per wave:
+//  * few edits (all claims of the wave fit one round): the claims (edited vertex, slot) are
+//    spread over the lanes, one stamp atomic per lane; winners appended with one atomic per list;
+//  * otherwise each edited lane claims its NV ring slots and NA anchors itself, with no branches
+//    between the atomics (a slot outside the grid issues a maximum with 0 on the vertex's own
+//    entry, which changes nothing), so all are in flight at once.
 template <int D>
 __device__ __forceinline__ void mark_neighbourhood(const FrontierView& B, const Dims& dm, bool changed, int v,
                                                    int it) {
     constexpr auto& g = G<D>::g;
     constexpr int NV = Geom<D>::NS + 1;
-    if (__ballot(changed) == 0) return;
+    constexpr int NA = g.naff;
+    constexpr int PER = NV + NA;
+    const unsigned long long mask = __ballot(changed);
+    if (mask == 0) return;
     const int nxt = (it + 1) & 1;
     Slot& N1 = slot_of(B, it + 1);
     const unsigned stamp = (unsigned)it + 1u;
+    int x = 0, y = 0, z = 0;
+    if (changed) coords(dm, v, x, y, z);
+    const int total = __popcll(mask) * PER;
+    if (total <= 64) {
+        const int cl = __lane_id();
+        const bool valid = cl < total;
+        const int k = valid ? cl / PER : 0;      // k-th edited lane of the wave
+        const int slot = valid ? cl - k * PER : 0;
+        unsigned long long m = mask;
+        for (int r = 0; r < k; r++) m &= m - 1ull;
+        const int src = __ffsll((long long)m) - 1;
+        const int vv = __shfl(v, src, 64);
+        const int sx = __shfl(x, src, 64), sy = __shfl(y, src, 64), sz = __shfl(z, src, 64);
+        int dx = 0, dy = 0, dz = 0;
+        const bool ring = slot < NV;
+        if (ring) {
+            if (slot > 0) { dx = g.slot_d[slot - 1][0]; dy = g.slot_d[slot - 1][1]; dz = g.slot_d[slot - 1][2]; }
+        } else {
+            dx = g.aff_d[slot - NV][0]; dy = g.aff_d[slot - NV][1]; dz = g.aff_d[slot - NV][2];
+        }
+        const bool ok = valid && (unsigned)(sx + dx) < (unsigned)dm.nx && (unsigned)(sy + dy) < (unsigned)dm.ny &&
+                        (unsigned)(sz + dz) < (unsigned)dm.nz;
+        const int t = vv + dx + dm.nx * dy + dm.nxy * dz;
+        bool won = false;
+        if (ok) won = atomicMax((ring ? B.vstamp : B.astamp[nxt]) + t, stamp) < stamp;
+        const int iv = wave_append(won && ring, &N1.n_dv);
+        const int ia = wave_append(won && !ring, &N1.n_da);
+        if (won) {
+            if (ring) B.dvl[nxt][iv] = t;
+            else B.dal[nxt][ia] = t;
+        }
+        return;
+    }
     uint32_t mv = 0;
     uint64_t ma = 0;
-    int x = 0, y = 0, z = 0;
     if (changed) {
-        coords(dm, v, x, y, z);
         unsigned* vs = B.vstamp;
         unsigned* as = B.astamp[nxt];
         unsigned ov[NV];
-        unsigned oa[g.naff];
+        unsigned oa[NA];
         uint32_t okv = 0;
         uint64_t oka = 0;
 #pragma unroll
@@ -240,7 +276,7 @@ __device__ __forceinline__ void mark_neighbourhood(const FrontierView& B, const 
             ov[s] = atomicMax(vs + (ok ? v + dx + dm.nx * dy + dm.nxy * dz : v), ok ? stamp : 0u);
         }
 #pragma unroll
-        for (int j = 0; j < g.naff; j++) {
+        for (int j = 0; j < NA; j++) {
             const int dx = g.aff_d[j][0], dy = g.aff_d[j][1], dz = g.aff_d[j][2];
             const bool ok = x + dx >= 0 && y + dy >= 0 && z + dz >= 0 && x + dx < dm.nx && y + dy < dm.ny &&
                             z + dz < dm.nz;
@@ -251,7 +287,7 @@ __device__ __forceinline__ void mark_neighbourhood(const FrontierView& B, const 
         for (int s = 0; s < NV; s++)
             if (((okv >> s) & 1u) && ov[s] < stamp) mv |= 1u << s;
 #pragma unroll
-        for (int j = 0; j < g.naff; j++)
+        for (int j = 0; j < NA; j++)
             if (((oka >> j) & 1ull) && oa[j] < stamp) ma |= 1ull << j;
     }
     int iv = wave_append_n(__popc(mv), &N1.n_dv);
@@ -269,7 +305,7 @@ __device__ __forceinline__ void mark_neighbourhood(const FrontierView& B, const 
         }
     }
 #pragma unroll
-    for (int j = 0; j < g.naff; j++) {
+    for (int j = 0; j < NA; j++) {
         if (ma & (1ull << j)) da[ia++] = v + g.aff_d[j][0] + dm.nx * g.aff_d[j][1] + dm.nxy * g.aff_d[j][2];
     }
 }
