@@ -13,6 +13,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "dmt_geom.h"
 
 namespace dmt {
@@ -201,10 +203,40 @@ __global__ void __launch_bounds__(256) k_minmax(const float* __restrict__ f, int
 //   triangle (v, a, b) if that triangle chose c, else a maximum.
 // Codes are scattered into the planes at the cells' anchors.
 
+// Compile-time loop: f(std::integral_constant<int, i>) for i = B .. E-1, so table lookups
+// indexed by i fold to constants (the loop bodies below index constexpr geometry tables).
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(static_cast<F&&>(f));
+    }
+}
+
+// c27 code of neighbour slot SLOT relative to the anchor at slot AS (-1: v itself).
+template <int D, int SLOT, int AS>
+__device__ __forceinline__ constexpr uint8_t c27rel() {
+    constexpr auto& g = G<D>::g;
+    constexpr int ax = AS < 0 ? 0 : g.slot_d[AS < 0 ? 0 : AS][0];
+    constexpr int ay = AS < 0 ? 0 : g.slot_d[AS < 0 ? 0 : AS][1];
+    constexpr int az = AS < 0 ? 0 : g.slot_d[AS < 0 ? 0 : AS][2];
+    return (uint8_t)c27_of(g.slot_d[SLOT][0] - ax, g.slot_d[SLOT][1] - ay, g.slot_d[SLOT][2] - az);
+}
+
+// Linear id of the anchor at neighbour slot AS of v (-1: v itself).
+template <int D, int AS>
+__device__ __forceinline__ int anchor_at(int v, const Dims& dm) {
+    if constexpr (AS < 0) {
+        return v;
+    } else {
+        constexpr auto& g = G<D>::g;
+        return v + g.slot_d[AS][0] + dm.nx * g.slot_d[AS][1] + dm.nxy * g.slot_d[AS][2];
+    }
+}
+
 template <int D>
 __device__ __forceinline__ void grad_vertex(const int v, const float* __restrict__ h, uint8_t* __restrict__ planes,
                                             const Dims& dm) {
-    constexpr auto& g = G<D>::g;
     constexpr int NS = Geom<D>::NS;
     constexpr int FULL = Geom<D>::FULL;
     constexpr int NTRI = Geom<D>::NTRI;
@@ -213,9 +245,9 @@ __device__ __forceinline__ void grad_vertex(const int v, const float* __restrict
     const float hv = h[v];
     float hn[NS];
     uint32_t L = 0;
-#pragma unroll
-    for (int s = 0; s < NS; s++) {
-        const int dx = g.slot_d[s][0], dy = g.slot_d[s][1], dz = g.slot_d[s][2];
+    static_for<0, NS>([&](auto sc) {
+        constexpr int s = decltype(sc)::value;
+        constexpr int dx = G<D>::g.slot_d[s][0], dy = G<D>::g.slot_d[s][1], dz = G<D>::g.slot_d[s][2];
         const bool ok = (unsigned)(x + dx) < (unsigned)dm.nx && (unsigned)(y + dy) < (unsigned)dm.ny &&
                         (unsigned)(z + dz) < (unsigned)dm.nz;
         // unconditional load (a neighbour outside the grid reads v itself) so that all loads are
@@ -225,109 +257,100 @@ __device__ __forceinline__ void grad_vertex(const int v, const float* __restrict
         // neighbour ids below v's are in slots < FULL: they win ties
         const bool lw = s < FULL ? (hn[s] <= hv) : (hn[s] < hv);
         L |= (uint32_t)(ok && lw) << s;
-    }
+    });
     // below[s] = lower neighbours that precede neighbour s (slot order = id order)
     uint32_t below[NS];
-#pragma unroll
-    for (int s = 0; s < NS; s++) below[s] = 0;
-#pragma unroll
-    for (int s = 0; s < NS; s++)
-#pragma unroll
-        for (int t = s + 1; t < NS; t++) {
+    static_for<0, NS>([&](auto sc) { below[decltype(sc)::value] = 0; });
+    static_for<0, NS>([&](auto sc) {
+        constexpr int s = decltype(sc)::value;
+        static_for<s + 1, NS>([&](auto tc) {
+            constexpr int t = decltype(tc)::value;
             const bool tb = hn[t] < hn[s];
             below[s] |= (uint32_t)tb << t;
             below[t] |= (uint32_t)(!tb) << s;
-        }
-#pragma unroll
-    for (int s = 0; s < NS; s++) below[s] &= L;
-
-    auto anchor_lin = [&](int aslot) -> int {
-        if (aslot < 0) return v;
-        return v + g.slot_d[aslot][0] + dm.nx * g.slot_d[aslot][1] + dm.nxy * g.slot_d[aslot][2];
-    };
-    auto c27rel = [&](int slot, int aslot) -> int {
-        int ax = aslot < 0 ? 0 : g.slot_d[aslot][0], ay = aslot < 0 ? 0 : g.slot_d[aslot][1],
-            az = aslot < 0 ? 0 : g.slot_d[aslot][2];
-        return c27_of(g.slot_d[slot][0] - ax, g.slot_d[slot][1] - ay, g.slot_d[slot][2] - az);
-    };
+        });
+    });
+    static_for<0, NS>([&](auto sc) { below[decltype(sc)::value] &= L; });
 
     // vertex
     int m = -1;
     uint8_t vcode = CODE_CRIT;
-#pragma unroll
-    for (int s = 0; s < NS; s++)
-        if (((L >> s) & 1) && below[s] == 0) { m = s; vcode = CODE_UP | c27rel(s, -1); }
+    static_for<0, NS>([&](auto sc) {
+        constexpr int s = decltype(sc)::value;
+        if (((L >> s) & 1) && below[s] == 0) { m = s; vcode = CODE_UP | c27rel<D, s, -1>(); }
+    });
     planes[v] = vcode;
 
     // edges (v, s)
     int emin[NS];
-#pragma unroll
-    for (int s = 0; s < NS; s++) {
+    static_for<0, NS>([&](auto sc) {
+        constexpr int s = decltype(sc)::value;
         emin[s] = -1;
-        if (!((L >> s) & 1)) continue;
-        const int as = g.edge_anchor_slot[s];
+        if (!((L >> s) & 1)) return;
+        constexpr int as = G<D>::g.edge_anchor_slot[s];
+        constexpr uint32_t trimask = G<D>::g.edge_trimask[s];
         uint8_t code;
         if (m == s) {
-            code = CODE_DOWN | c27rel(s, as);
+            code = CODE_DOWN | c27rel<D, s, as>();
         } else {
-            const uint32_t cand = g.edge_trimask[s] & below[s];
+            const uint32_t cand = trimask & below[s];
             code = CODE_CRIT;
-#pragma unroll
-            for (int t = 0; t < NS; t++) {
-                if (!((g.edge_trimask[s] >> t) & 1)) continue;
-                if (((cand >> t) & 1) && (below[t] & cand) == 0) { emin[s] = t; code = CODE_UP | c27rel(t, as); }
-            }
+            static_for<0, NS>([&](auto tc) {
+                constexpr int t = decltype(tc)::value;
+                if constexpr (((trimask >> t) & 1u) != 0u) {
+                    if (((cand >> t) & 1) && (below[t] & cand) == 0) { emin[s] = t; code = CODE_UP | c27rel<D, t, as>(); }
+                }
+            });
         }
-        planes[(size_t)g.edge_plane[s] * dm.n + anchor_lin(as)] = code;
-    }
+        planes[(size_t)G<D>::g.edge_plane[s] * dm.n + anchor_at<D, as>(v, dm)] = code;
+    });
 
     // triangles (v, s, t)
     int tmin[NTRI];
-#pragma unroll
-    for (int i = 0; i < NTRI; i++) {
+    static_for<0, NTRI>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        constexpr int s = G<D>::g.tri_s[i], t = G<D>::g.tri_t[i];
         tmin[i] = -1;
-        const int s = g.tri_s[i], t = g.tri_t[i];
-        if (!((L >> s) & 1) || !((L >> t) & 1)) continue;
-        const int as = g.tri_anchor_slot[i];
+        if (!((L >> s) & 1) || !((L >> t) & 1)) return;
+        constexpr int as = G<D>::g.tri_anchor_slot[i];
         const bool t_below_s = (below[s] >> t) & 1;   // then s is the middle vertex, t the lowest
         const bool claimed = t_below_s ? (emin[s] == t) : (emin[t] == s);
         uint8_t code;
         if (claimed) {
-            code = CODE_DOWN | (t_below_s ? c27rel(t, as) : c27rel(s, as));
+            code = CODE_DOWN | (t_below_s ? c27rel<D, t, as>() : c27rel<D, s, as>());
         } else {
             code = CODE_CRIT;
-            if (D == 3) {
-                const uint32_t cand = g.tri_tetmask[i] & (t_below_s ? below[t] : below[s]);
-#pragma unroll
-                for (int u = 0; u < NS; u++) {
-                    if (!((g.tri_tetmask[i] >> u) & 1)) continue;
-                    if (((cand >> u) & 1) && (below[u] & cand) == 0) { tmin[i] = u; code = CODE_UP | c27rel(u, as); }
-                }
+            if constexpr (D == 3) {
+                constexpr uint32_t tetmask = G<D>::g.tri_tetmask[i];
+                const uint32_t cand = tetmask & (t_below_s ? below[t] : below[s]);
+                static_for<0, NS>([&](auto uc) {
+                    constexpr int u = decltype(uc)::value;
+                    if constexpr (((tetmask >> u) & 1u) != 0u) {
+                        if (((cand >> u) & 1) && (below[u] & cand) == 0) { tmin[i] = u; code = CODE_UP | c27rel<D, u, as>(); }
+                    }
+                });
             }
         }
-        planes[(size_t)g.tri_plane[i] * dm.n + anchor_lin(as)] = code;
-    }
+        planes[(size_t)G<D>::g.tri_plane[i] * dm.n + anchor_at<D, as>(v, dm)] = code;
+    });
 
     // tetrahedra (v, s, t, u)
-    if (D == 3) {
-#pragma unroll
-        for (int i = 0; i < Geom<D>::NTET; i++) {
-            const int s = g.tet_s[i], t = g.tet_t[i], u = g.tet_u[i];
-            if (!((L >> s) & 1) || !((L >> t) & 1) || !((L >> u) & 1)) continue;
-            const int as = g.tet_anchor_slot[i];
+    if constexpr (D == 3) {
+        static_for<0, Geom<D>::NTET>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            constexpr int s = G<D>::g.tet_s[i], t = G<D>::g.tet_t[i], u = G<D>::g.tet_u[i];
+            if (!((L >> s) & 1) || !((L >> t) & 1) || !((L >> u) & 1)) return;
+            constexpr int as = G<D>::g.tet_anchor_slot[i];
             const bool t_s = (below[s] >> t) & 1, u_s = (below[s] >> u) & 1, u_t = (below[t] >> u) & 1;
             // lowest of the three, and the top triangle made of v and the other two
-            int low, top;
+            int low, tm;
             uint8_t downc;
-            if (u_s && u_t) { low = u; top = g.tri_index[s][t]; downc = CODE_DOWN | c27rel(u, as); }
-            else if (t_s && !u_t) { low = t; top = g.tri_index[s][u]; downc = CODE_DOWN | c27rel(t, as); }
-            else { low = s; top = g.tri_index[t][u]; downc = CODE_DOWN | c27rel(s, as); }
-            int tm = -1;
-#pragma unroll
-            for (int k = 0; k < NTRI; k++) if (k == top) tm = tmin[k];
+            if (u_s && u_t) { low = u; tm = tmin[G<D>::g.tri_index[s][t]]; downc = CODE_DOWN | c27rel<D, u, as>(); }
+            else if (t_s && !u_t) { low = t; tm = tmin[G<D>::g.tri_index[s][u]]; downc = CODE_DOWN | c27rel<D, t, as>(); }
+            else { low = s; tm = tmin[G<D>::g.tri_index[t][u]]; downc = CODE_DOWN | c27rel<D, s, as>(); }
             const uint8_t code = (tm == low) ? downc : CODE_CRIT;
-            planes[(size_t)g.tet_plane[i] * dm.n + anchor_lin(as)] = code;
-        }
+            planes[(size_t)G<D>::g.tet_plane[i] * dm.n + anchor_at<D, as>(v, dm)] = code;
+        });
     }
 }
 
