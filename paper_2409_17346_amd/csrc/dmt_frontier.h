@@ -365,24 +365,26 @@ __device__ __forceinline__ int plane_target(const FrontierView& B, const Dims& d
     int best = -1;
     float gbest = 0.0f;
     int kx = 0;
-#pragma unroll
-    for (int k = 0; k < g.bnv[P]; k++) {
-        const int ck = c27_of(g.bvert[P][k][0], g.bvert[P][k][1], g.bvert[P][k][2]);
-        if (!up && ck == gx) { kx = k; continue; }
-        const int w = a + g.bvert[P][k][0] + dm.nx * g.bvert[P][k][1] + dm.nxy * g.bvert[P][k][2];
-        if (!prec(B.f[w], w, fx, xv)) continue;
+    static_for<0, g.bnv[P]>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        constexpr int bx = G<D>::g.bvert[P][k][0], by = G<D>::g.bvert[P][k][1], bz = G<D>::g.bvert[P][k][2];
+        constexpr int ck = c27_of(bx, by, bz);
+        if (!up && ck == gx) { kx = k; return; }
+        const int w = a + bx + dm.nx * by + dm.nxy * bz;
+        if (!prec(B.f[w], w, fx, xv)) return;
         const float gw = gcur[w];
         if (best < 0 || prec(gw, w, gbest, best)) { best = w; gbest = gw; }
-    }
+    });
     if (best < 0) {
         int fa = a, fp = 0;
-#pragma unroll
-        for (int k = 0; k < g.bnv[P]; k++) {
+        static_for<0, g.bnv[P]>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
             if (k == kx) {
-                fa = a + g.facet_anchor[P][k][0] + dm.nx * g.facet_anchor[P][k][1] + dm.nxy * g.facet_anchor[P][k][2];
-                fp = g.facet_plane[P][k];
+                fa = a + G<D>::g.facet_anchor[P][k][0] + dm.nx * G<D>::g.facet_anchor[P][k][1] +
+                     dm.nxy * G<D>::g.facet_anchor[P][k][2];
+                fp = G<D>::g.facet_plane[P][k];
             }
-        }
+        });
         best = fa + c27_lin(dm, B.fpl[(size_t)fp * dm.n + fa] & 63);
     }
     cnt[2 * dim + 1]++;
@@ -937,20 +939,22 @@ __global__ void __launch_bounds__(256) k_fr_branch_map(FrontierBufs hb, int pass
         const int a = T / g.ntypes[D];
         const int tp = T - a * g.ntypes[D] + g.base[D];
         v = a;
-#pragma unroll
-        for (int q = g.base[D]; q < g.base[D] + g.ntypes[D]; q++) {
-            if (q != tp) continue;
-#pragma unroll
-            for (int r = 0; r <= D; r++)
-                if (r == j) v = a + g.bvert[q][r][0] + dm.nx * g.bvert[q][r][1] + dm.nxy * g.bvert[q][r][2];
-        }
+        static_for<g.base[D], g.base[D] + g.ntypes[D]>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            if (q != tp) return;
+            static_for<0, D + 1>([&](auto rc) {
+                constexpr int r = decltype(rc)::value;
+                constexpr auto& gg = G<D>::g;
+                if (r == j) v = a + gg.bvert[q][r][0] + dm.nx * gg.bvert[q][r][1] + dm.nxy * gg.bvert[q][r][2];
+            });
+        });
         kk = (int)(B.n_dcell + k);
     }
     if (pass == 0) atomicAdd(&pos[v], 1);
     else ecell[atomicAdd(&pos[v], 1)] = kk;
 }
 
-// ---- launch-per-phase form (when a cooperative launch is not available) --------------------
+// ---- launch-per-phase form: one full-grid launch per phase --------------------------------
 
 __device__ __forceinline__ bool running(const Ctl* c) { return ld_relaxed(&c->done) == 0; }
 

@@ -213,15 +213,16 @@ __device__ __forceinline__ void static_for(F&& f) {
     }
 }
 
-// c27 code of neighbour slot SLOT relative to the anchor at slot AS (-1: v itself).
+// c27 code of neighbour slot SLOT relative to the anchor at slot AS (-1: v itself), as a
+// compile-time constant (a static member, so uses never read the table at run time).
 template <int D, int SLOT, int AS>
-__device__ __forceinline__ constexpr uint8_t c27rel() {
-    constexpr auto& g = G<D>::g;
-    constexpr int ax = AS < 0 ? 0 : g.slot_d[AS < 0 ? 0 : AS][0];
-    constexpr int ay = AS < 0 ? 0 : g.slot_d[AS < 0 ? 0 : AS][1];
-    constexpr int az = AS < 0 ? 0 : g.slot_d[AS < 0 ? 0 : AS][2];
-    return (uint8_t)c27_of(g.slot_d[SLOT][0] - ax, g.slot_d[SLOT][1] - ay, g.slot_d[SLOT][2] - az);
-}
+struct C27Rel {
+    static constexpr int ax = AS < 0 ? 0 : G<D>::g.slot_d[AS < 0 ? 0 : AS][0];
+    static constexpr int ay = AS < 0 ? 0 : G<D>::g.slot_d[AS < 0 ? 0 : AS][1];
+    static constexpr int az = AS < 0 ? 0 : G<D>::g.slot_d[AS < 0 ? 0 : AS][2];
+    static constexpr uint8_t value = (uint8_t)c27_of(G<D>::g.slot_d[SLOT][0] - ax, G<D>::g.slot_d[SLOT][1] - ay,
+                                                     G<D>::g.slot_d[SLOT][2] - az);
+};
 
 // Linear id of the anchor at neighbour slot AS of v (-1: v itself).
 template <int D, int AS>
@@ -277,7 +278,7 @@ __device__ __forceinline__ void grad_vertex(const int v, const float* __restrict
     uint8_t vcode = CODE_CRIT;
     static_for<0, NS>([&](auto sc) {
         constexpr int s = decltype(sc)::value;
-        if (((L >> s) & 1) && below[s] == 0) { m = s; vcode = CODE_UP | c27rel<D, s, -1>(); }
+        if (((L >> s) & 1) && below[s] == 0) { m = s; vcode = CODE_UP | C27Rel<D, s, -1>::value; }
     });
     planes[v] = vcode;
 
@@ -291,14 +292,14 @@ __device__ __forceinline__ void grad_vertex(const int v, const float* __restrict
         constexpr uint32_t trimask = G<D>::g.edge_trimask[s];
         uint8_t code;
         if (m == s) {
-            code = CODE_DOWN | c27rel<D, s, as>();
+            code = CODE_DOWN | C27Rel<D, s, as>::value;
         } else {
             const uint32_t cand = trimask & below[s];
             code = CODE_CRIT;
             static_for<0, NS>([&](auto tc) {
                 constexpr int t = decltype(tc)::value;
                 if constexpr (((trimask >> t) & 1u) != 0u) {
-                    if (((cand >> t) & 1) && (below[t] & cand) == 0) { emin[s] = t; code = CODE_UP | c27rel<D, t, as>(); }
+                    if (((cand >> t) & 1) && (below[t] & cand) == 0) { emin[s] = t; code = CODE_UP | C27Rel<D, t, as>::value; }
                 }
             });
         }
@@ -317,7 +318,7 @@ __device__ __forceinline__ void grad_vertex(const int v, const float* __restrict
         const bool claimed = t_below_s ? (emin[s] == t) : (emin[t] == s);
         uint8_t code;
         if (claimed) {
-            code = CODE_DOWN | (t_below_s ? c27rel<D, t, as>() : c27rel<D, s, as>());
+            code = CODE_DOWN | (t_below_s ? C27Rel<D, t, as>::value : C27Rel<D, s, as>::value);
         } else {
             code = CODE_CRIT;
             if constexpr (D == 3) {
@@ -326,7 +327,7 @@ __device__ __forceinline__ void grad_vertex(const int v, const float* __restrict
                 static_for<0, NS>([&](auto uc) {
                     constexpr int u = decltype(uc)::value;
                     if constexpr (((tetmask >> u) & 1u) != 0u) {
-                        if (((cand >> u) & 1) && (below[u] & cand) == 0) { tmin[i] = u; code = CODE_UP | c27rel<D, u, as>(); }
+                        if (((cand >> u) & 1) && (below[u] & cand) == 0) { tmin[i] = u; code = CODE_UP | C27Rel<D, u, as>::value; }
                     }
                 });
             }
@@ -345,9 +346,9 @@ __device__ __forceinline__ void grad_vertex(const int v, const float* __restrict
             // lowest of the three, and the top triangle made of v and the other two
             int low, tm;
             uint8_t downc;
-            if (u_s && u_t) { low = u; tm = tmin[G<D>::g.tri_index[s][t]]; downc = CODE_DOWN | c27rel<D, u, as>(); }
-            else if (t_s && !u_t) { low = t; tm = tmin[G<D>::g.tri_index[s][u]]; downc = CODE_DOWN | c27rel<D, t, as>(); }
-            else { low = s; tm = tmin[G<D>::g.tri_index[t][u]]; downc = CODE_DOWN | c27rel<D, s, as>(); }
+            if (u_s && u_t) { low = u; tm = tmin[G<D>::g.tri_index[s][t]]; downc = CODE_DOWN | C27Rel<D, u, as>::value; }
+            else if (t_s && !u_t) { low = t; tm = tmin[G<D>::g.tri_index[s][u]]; downc = CODE_DOWN | C27Rel<D, t, as>::value; }
+            else { low = s; tm = tmin[G<D>::g.tri_index[t][u]]; downc = CODE_DOWN | C27Rel<D, s, as>::value; }
             const uint8_t code = (tm == low) ? downc : CODE_CRIT;
             planes[(size_t)G<D>::g.tet_plane[i] * dm.n + anchor_at<D, as>(v, dm)] = code;
         });
@@ -692,28 +693,28 @@ __device__ __forceinline__ int top_id(int a, int tp) {
 // On a boundary exit sets a = -1.
 template <int D>
 __device__ __forceinline__ bool asc_step(const Dims& dm, const uint8_t* __restrict__ pl, int& a, int& tp) {
-    constexpr auto& g = G<D>::g;
     const uint8_t code = pl[(size_t)tp * dm.n + a];
     if (code == CODE_CRIT) return false;
     const int c = code & 63;
     int x, y, z;
     coords(dm, a, x, y, z);
     int na = -1, np = -1;
-#pragma unroll
-    for (int q = g.base[D]; q < g.base[D] + g.ntypes[D]; q++) {
-        if (q != tp) continue;
-#pragma unroll
-        for (int k = 0; k <= D; k++) {
-            if (c != c27_of(g.bvert[q][k][0], g.bvert[q][k][1], g.bvert[q][k][2])) continue;
+    constexpr int B0 = G<D>::g.base[D], NT = G<D>::g.ntypes[D];
+    static_for<B0, B0 + NT>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        if (q != tp) return;
+        static_for<0, D + 1>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            constexpr auto& g = G<D>::g;
+            if (c != c27_of(g.bvert[q][k][0], g.bvert[q][k][1], g.bvert[q][k][2])) return;
             const int ax = x + g.nbr_anchor[q][k][0], ay = y + g.nbr_anchor[q][k][1], az = z + g.nbr_anchor[q][k][2];
-            const int p2 = g.nbr_plane[q][k];
+            constexpr int p2 = g.nbr_plane[q][k];
             bool ok = ax >= 0 && ay >= 0 && az >= 0;
-#pragma unroll
-            for (int r = g.base[D]; r < g.base[D] + g.ntypes[D]; r++)
-                if (r == p2) ok = ok && ax + g.bmax[r][0] < dm.nx && ay + g.bmax[r][1] < dm.ny && az + g.bmax[r][2] < dm.nz;
+            if constexpr (p2 >= B0 && p2 < B0 + NT)
+                ok = ok && ax + g.bmax[p2][0] < dm.nx && ay + g.bmax[p2][1] < dm.ny && az + g.bmax[p2][2] < dm.nz;
             if (ok) { na = ax + dm.nx * ay + dm.nxy * az; np = p2; }
-        }
-    }
+        });
+    });
     a = na;
     tp = np;
     return true;
