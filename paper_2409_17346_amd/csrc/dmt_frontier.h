@@ -168,7 +168,16 @@ __device__ __forceinline__ bool wave_done(int base, int gtid, int n) {
     return base + (gtid & ~63) >= n;
 }
 
-__device__ __forceinline__ Slot& slot_of(const FrontierView& B, int it) { return B.ctl->slot[it % 3]; }
+// The counter slots of the workgroup-resident loop live in LDS while the loop runs (copied in
+// from the job's control block when it starts and back when it stops); the full-grid phases
+// use the control block itself.
+__shared__ Slot wg_slots[3];
+
+template <bool WG = false>
+__device__ __forceinline__ Slot& slot_of(const FrontierView& B, int it) {
+    if constexpr (WG) return wg_slots[it % 3];
+    else return B.ctl->slot[it % 3];
+}
 
 __device__ __forceinline__ unsigned long long c_total(const Slot& s) {
     unsigned long long t = 0;
@@ -211,7 +220,7 @@ __device__ __forceinline__ bool apply_vertex(const FrontierView& B, int v, int i
 //  * otherwise each edited lane claims its NV ring slots and NA anchors itself, with no branches
 //    between the atomics (a slot outside the grid issues a maximum with 0 on the vertex's own
 //    entry, which changes nothing), so all are in flight at once.
-template <int D>
+template <int D, bool WG = false>
 __device__ __forceinline__ void mark_neighbourhood(const FrontierView& B, const Dims& dm, bool changed, int v,
                                                    int it) {
     constexpr auto& g = G<D>::g;
@@ -221,7 +230,7 @@ __device__ __forceinline__ void mark_neighbourhood(const FrontierView& B, const 
     const unsigned long long mask = __ballot(changed);
     if (mask == 0) return;
     const int nxt = (it + 1) & 1;
-    Slot& N1 = slot_of(B, it + 1);
+    Slot& N1 = slot_of<WG>(B, it + 1);
     const unsigned stamp = (unsigned)it + 1u;
     int x = 0, y = 0, z = 0;
     if (changed) coords(dm, v, x, y, z);
@@ -312,7 +321,7 @@ __device__ __forceinline__ void mark_neighbourhood(const FrontierView& B, const 
 
 // Request of vertex v (v < 0: none) in iteration it: the first requester counts it in rc[0]
 // and, when edits are allowed, edits it (counted in rc[1]) and marks its neighbourhood.
-template <int D>
+template <int D, bool WG = false>
 __device__ __forceinline__ void request_apply(const FrontierView& B, const Dims& dm, int v, int it, bool edit,
                                               int* rc) {
     const unsigned stamp = (unsigned)it + 1u;
@@ -328,7 +337,7 @@ __device__ __forceinline__ void request_apply(const FrontierView& B, const Dims&
             if (changed) rc[1]++;
         }
     }
-    mark_neighbourhood<D>(B, dm, changed, v, it);
+    mark_neighbourhood<D, WG>(B, dm, changed, v, it);
 }
 
 // ---- violation mask of one anchor: planes whose criticality differs between f and g --------
@@ -402,7 +411,7 @@ __device__ __forceinline__ int plane_target_dyn(int p, const FrontierView& B, co
 
 // Requests (and, with edit, edits) the targets of the violating planes m of anchor a.  Whole
 // waves call it; lanes without an anchor pass m = 0.  One plane per lane per round.
-template <int D>
+template <int D, bool WG = false>
 __device__ __forceinline__ void anchor_requests(const FrontierView& B, const Dims& dm, int a, uint32_t m, int it,
                                                 bool edit, int* cnt, int* rc) {
     const float* gcur = B.gb[it & 1];
@@ -414,7 +423,7 @@ __device__ __forceinline__ void anchor_requests(const FrontierView& B, const Dim
             m &= m - 1u;
             target = plane_target_dyn<D, 0>(p, B, dm, a, gcur, cnt);
         }
-        request_apply<D>(B, dm, target, it, edit, rc);
+        request_apply<D, WG>(B, dm, target, it, edit, rc);
     }
 }
 
@@ -423,10 +432,10 @@ __device__ __forceinline__ void anchor_requests(const FrontierView& B, const Dim
 // Gradient of g^(it) for the dirty vertices (every vertex at iteration 0); brings the write
 // buffer up to date on them; lists the cells of f's branches that contain a dirty vertex (the
 // only branch cells whose pairing can have changed); clears the next slot.
-template <int D>
+template <int D, bool WG = false>
 __device__ __forceinline__ void phase_grad(const FrontierView& B, const Dims& dm, int it, int gtid, int gsize) {
     if (gtid == 0) {
-        Slot& s = slot_of(B, it + 1);
+        Slot& s = slot_of<WG>(B, it + 1);
         for (int k = 0; k < CNT_WORDS; k++) s.cnt[k] = 0;
         s.n_dv = s.n_da = s.n_vl = s.n_tc = s.n_db = s.n_scan = 0;
     }
@@ -436,7 +445,7 @@ __device__ __forceinline__ void phase_grad(const FrontierView& B, const Dims& dm
         for (int i = gtid; i < dm.n; i += gsize) grad_vertex<D>(i, gcur, B.gpl, dm);
         return;
     }
-    Slot& S = slot_of(B, it);
+    Slot& S = slot_of<WG>(B, it);
     const int n = ld_relaxed(&S.n_dv);
     const int* list = B.dvl[it & 1];
     for (int base = 0; base < n; base += gsize) {
@@ -485,9 +494,9 @@ __device__ __forceinline__ bool branch_cell_differs(const FrontierView& B, const
 // differed, and only the touched cells can have changed since.
 // Pass A (touched_cells): each touched cell marks its branch and, if it differs now, lowers
 // newmin[branch] to it.
-template <int D>
+template <int D, bool WG = false>
 __device__ __forceinline__ void touched_cells(const FrontierView& B, const Dims& dm, int it, int gtid, int gsize) {
-    Slot& S = slot_of(B, it);
+    Slot& S = slot_of<WG>(B, it);
     const int n = ld_relaxed(&S.n_tc);
     const unsigned stamp = (unsigned)it + 1u;
     for (int base = 0; base < n; base += gsize) {
@@ -511,10 +520,10 @@ __device__ __forceinline__ void touched_cells(const FrontierView& B, const Dims&
 // Pass B (phase_bscan): for each marked branch, if its old first cell still differs the new
 // first is the smaller of it and newmin; otherwise the first differing cell after the old first
 // (searched only up to newmin), else newmin.  One wave per branch, 64 cells per step.
-template <int D>
+template <int D, bool WG = false>
 __device__ __forceinline__ void phase_bscan(const FrontierView& B, const Dims& dm, int it, int gtid, int gsize) {
     if (it == 0 || B.tier < 3) return;
-    Slot& S = slot_of(B, it);
+    Slot& S = slot_of<WG>(B, it);
     const int n = ld_relaxed(&S.n_db);
     const int lane = __lane_id();
     const int sel = ld_relaxed(&B.ctl->cand_sel);
@@ -561,11 +570,11 @@ __device__ __forceinline__ void phase_bscan(const FrontierView& B, const Dims& d
 // Violation masks of the affected anchors (every anchor at iteration 0), the targets of every
 // violating anchor (edited at once when edit is set), the violation list of the next iteration,
 // and the speculative first-difference scan along f's branches.
-template <int D>
+template <int D, bool WG = false>
 __device__ __forceinline__ void phase_vr(const FrontierView& B, const Dims& dm, int it, bool edit, int gtid,
                                          int gsize) {
-    Slot& S = slot_of(B, it);
-    int* n_next = &slot_of(B, it + 1).n_vl;
+    Slot& S = slot_of<WG>(B, it);
+    int* n_next = &slot_of<WG>(B, it + 1).n_vl;
     int* next = B.vl[(it + 1) & 1];
     int cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     int rc[2] = {0, 0};
@@ -595,7 +604,7 @@ __device__ __forceinline__ void phase_vr(const FrontierView& B, const Dims& dm, 
         }
         const int idx = wave_append(m != 0, n_next);
         if (m != 0) next[idx] = a;
-        anchor_requests<D>(B, dm, a, m, it, edit, cnt, rc);
+        anchor_requests<D, WG>(B, dm, a, m, it, edit, cnt, rc);
     }
     // first differing cell of the f-branches, kept up to date for the separatrix step: every
     // branch at iteration 0 (first[] starts at INF32), afterwards the branches listed by the
@@ -607,7 +616,7 @@ __device__ __forceinline__ void phase_vr(const FrontierView& B, const Dims& dm, 
             for (long long k = gtid; k < B.n_acell; k += gsize)
                 if (branch_cell_differs<D>(B, dm, true, k)) atomicMin(&B.afirst[B.acbr[k]], (int)k);
         } else {
-            touched_cells<D>(B, dm, it, gtid, gsize);
+            touched_cells<D, WG>(B, dm, it, gtid, gsize);
         }
     }
     block_add_counters<8>(S.cnt + CNT_FP0, cnt);
@@ -616,7 +625,7 @@ __device__ __forceinline__ void phase_vr(const FrontierView& B, const Dims& dm, 
 
 // Troublemaker targets (apex of the f-pair of each branch's first differing cell), edited at
 // once.  Only called when iteration it has no critical-cell violation.
-template <int D>
+template <int D, bool WG = false>
 __device__ __forceinline__ void phase_sapply(const FrontierView& B, const Dims& dm, int it, bool edit, int gtid,
                                              int gsize) {
     constexpr auto& g = G<D>::g;
@@ -686,10 +695,10 @@ __device__ __forceinline__ void phase_sapply(const FrontierView& B, const Dims& 
         }
         const int idx = wave_append(kept, &B.ctl->n_cand[sel ^ 1]);
         if (kept) keep[idx] = bb;
-        request_apply<D>(B, dm, target, it, edit, rc);
+        request_apply<D, WG>(B, dm, target, it, edit, rc);
     }
-    block_add_counters<2>(slot_of(B, it).cnt + CNT_TM_DESC, c);
-    block_add_counters<2>(slot_of(B, it).cnt + CNT_NREQ, rc);
+    block_add_counters<2>(slot_of<WG>(B, it).cnt + CNT_TM_DESC, c);
+    block_add_counters<2>(slot_of<WG>(B, it).cnt + CNT_NREQ, rc);
 }
 
 // ---- iteration bookkeeping ----------------------------------------------------------------
@@ -772,8 +781,9 @@ __device__ __forceinline__ void cand_flip(Ctl* c) {
 
 // iteration_state and record_iteration for a whole wave (wave 0 of the workgroup): lane k
 // loads counter k, so the loads are issued together, and writes log word k.
+template <bool WG>
 __device__ __forceinline__ int wave_decide(const FrontierView& B, int it, int lane) {
-    const Slot& S = slot_of(B, it);
+    const Slot& S = slot_of<WG>(B, it);
     const unsigned long long v = lane < CNT_WORDS ? ld_relaxed(&S.cnt[lane]) : 0ull;
     const unsigned long long cv = (lane >= CNT_FP0 && lane < CNT_FP0 + 8) ? v : 0ull;
     const unsigned long long tv = (lane == CNT_TM_DESC || lane == CNT_TM_ASC) ? v : 0ull;
@@ -826,6 +836,14 @@ __device__ __forceinline__ void run_job_wg(const FrontierView& B, int max_passes
     const int tid = threadIdx.x, nt = blockDim.x;
     if (ld_relaxed(&c->done)) return;
     int it = ld_relaxed(&c->it);
+    constexpr int SLOT_WORDS = (int)(3 * sizeof(Slot) / sizeof(int));
+    static_assert(sizeof(Slot) % sizeof(int) == 0, "slots copied as ints");
+    {
+        const int* src = reinterpret_cast<const int*>(c->slot);
+        int* dst = reinterpret_cast<int*>(wg_slots);
+        for (int k = tid; k < SLOT_WORDS; k += nt) dst[k] = src[k];
+    }
+    __syncthreads();
     unsigned long long ph[3] = {0, 0, 0};
     unsigned long long t = tid == 0 ? wall_clock64() : 0;
     unsigned long long t_it = t;   // start of the current iteration's gradient pass
@@ -838,7 +856,7 @@ __device__ __forceinline__ void run_job_wg(const FrontierView& B, int max_passes
     for (int pass = 0; pass < max_passes; pass++) {
         if (B.log && it >= B.log_cap) break;
         if (tid < 64) {
-            const bool s_step = B.tier >= 3 && c_total(slot_of(B, it)) == 0;
+            const bool s_step = B.tier >= 3 && c_total(slot_of<true>(B, it)) == 0;
             int act = s_step;
             // a troublemaker pass over more than `big` candidates is left to the grid too
             if (s_step && big > 0 && ld_relaxed(&c->n_cand[ld_relaxed(&c->cand_sel)]) > big) {
@@ -850,11 +868,11 @@ __device__ __forceinline__ void run_job_wg(const FrontierView& B, int max_passes
         __syncthreads();
         if (sstep_sh == 2) break;
         if (sstep_sh) {
-            phase_sapply<D>(B, dm, it, (long long)it != B.max_iters, tid, nt);
+            phase_sapply<D, true>(B, dm, it, (long long)it != B.max_iters, tid, nt);
             __syncthreads();
         }
         if (tid < 64) {
-            const int st = wave_decide(B, it, tid);
+            const int st = wave_decide<true>(B, it, tid);
             if (tid == 0) {
                 if (B.log && st == 0) B.log[(size_t)it * DMT_LOG_WORDS + 19] = (long long)(wall_clock64() - t_it);
                 c->it = st ? it : it + 1;
@@ -862,7 +880,7 @@ __device__ __forceinline__ void run_job_wg(const FrontierView& B, int max_passes
                 int act = st;
                 // a large next iteration is left to full-grid launches: pause before its gradient pass
                 if (st == 0 && big > 0) {
-                    const Slot& N = slot_of(B, it + 1);
+                    const Slot& N = slot_of<true>(B, it + 1);
                     if (ld_relaxed(&N.n_da) + ld_relaxed(&N.n_vl) > big) {
                         c->paused = 1;
                         act = 4;
@@ -877,16 +895,22 @@ __device__ __forceinline__ void run_job_wg(const FrontierView& B, int max_passes
         if (st) break;
         it++;
         if (tid == 0) t_it = wall_clock64();
-        phase_grad<D>(B, dm, it, tid, nt);
+        phase_grad<D, true>(B, dm, it, tid, nt);
         __syncthreads();
         tick(1);
-        phase_vr<D>(B, dm, it, (long long)it != B.max_iters, tid, nt);
+        phase_vr<D, true>(B, dm, it, (long long)it != B.max_iters, tid, nt);
         __syncthreads();
         if (B.tier >= 3) {
-            phase_bscan<D>(B, dm, it, tid, nt);
+            phase_bscan<D, true>(B, dm, it, tid, nt);
             __syncthreads();
         }
         tick(2);
+    }
+    __syncthreads();
+    {
+        const int* src = reinterpret_cast<const int*>(wg_slots);
+        int* dst = reinterpret_cast<int*>(c->slot);
+        for (int k = tid; k < SLOT_WORDS; k += nt) dst[k] = src[k];
     }
     if (tid == 0)
         for (int k = 0; k < 3; k++) c->ph[k] += ph[k];
