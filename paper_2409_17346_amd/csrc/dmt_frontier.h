@@ -409,6 +409,27 @@ __device__ __forceinline__ int plane_target_dyn(int p, const FrontierView& B, co
     return -1;
 }
 
+// Target of violating plane p (chosen at run time) of anchor a: a false positive (the cell is
+// paired in f) takes the apex of its f-pair on one code path for every plane, so a wave whose
+// lanes hold different planes does not run one path per plane; false negatives (rare) go through
+// the per-plane code.
+template <int D>
+__device__ __forceinline__ int plane_target_any(int p, const FrontierView& B, const Dims& dm, int a, const float* gcur,
+                                                int* cnt) {
+    constexpr auto& g = G<D>::g;
+    const uint8_t fc = B.fpl[(size_t)p * dm.n + a];
+    if (fc != CODE_CRIT) {
+        int dim = (p >= g.base[1]) + (p >= g.base[2]);
+        if constexpr (D == 3) dim += (p >= g.base[3]);
+        static_for<0, D + 1>([&](auto dc) {
+            constexpr int d = decltype(dc)::value;
+            if (dim == d) cnt[2 * d]++;
+        });
+        return a + c27_lin(dm, fc & 63);
+    }
+    return plane_target_dyn<D, 0>(p, B, dm, a, gcur, cnt);
+}
+
 // Requests (and, with edit, edits) the targets of the violating planes m of anchor a.  Whole
 // waves call it; lanes without an anchor pass m = 0.  One plane per lane per round.
 template <int D, bool WG = false>
@@ -421,7 +442,7 @@ __device__ __forceinline__ void anchor_requests(const FrontierView& B, const Dim
         if (m != 0) {
             const int p = __ffs(m) - 1;
             m &= m - 1u;
-            target = plane_target_dyn<D, 0>(p, B, dm, a, gcur, cnt);
+            target = plane_target_any<D>(p, B, dm, a, gcur, cnt);
         }
         request_apply<D, WG>(B, dm, target, it, edit, rc);
     }
