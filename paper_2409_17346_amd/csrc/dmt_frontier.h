@@ -670,7 +670,6 @@ __device__ __forceinline__ void phase_sapply(const FrontierView& B, const Dims& 
             const int b = asc ? bb - B.n_desc : bb;
             const int* first = asc ? B.afirst : B.dfirst;
             const int* cells = asc ? B.acell : B.dcell;
-            const int64_t* off = asc ? B.aoff : B.doff;
             const int* term = asc ? B.aterm : B.dterm;
             const int k = first[b];
             kept = k != INF32;
@@ -678,9 +677,11 @@ __device__ __forceinline__ void phase_sapply(const FrontierView& B, const Dims& 
             if (k != INF32) {
                 bool ok = true;
                 if (B.tier == 3) {
+                    // cells before k are paired alike in f and g, so g's path from the branch's
+                    // start passes through cell k: its walk starts there
                     int gt;
                     if (!asc) {
-                        int v = cells[off[b]];
+                        int v = cells[k];
                         for (int step = 0; step < dm.n; step++) {
                             const uint8_t cc = B.gpl[v];
                             if (cc == CODE_CRIT) break;
@@ -688,7 +689,7 @@ __device__ __forceinline__ void phase_sapply(const FrontierView& B, const Dims& 
                         }
                         gt = v;
                     } else {
-                        const int T0 = cells[off[b]];
+                        const int T0 = cells[k];
                         int a = T0 / g.ntypes[D];
                         int tp = T0 - a * g.ntypes[D] + g.base[D];
                         gt = -1;
