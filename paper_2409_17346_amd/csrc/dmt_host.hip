@@ -31,6 +31,7 @@ struct DevBuf {
 };
 
 constexpr int TPB = 256;
+constexpr int HAND_STREAMS = 4;  // streams for the grid iterations of paused batch jobs
 inline unsigned nblocks(int64_t n) { return (unsigned)((n + TPB - 1) / TPB); }
 
 // Critical cells and separatrix branches of one gradient (device arrays, int32 ids).
@@ -78,6 +79,10 @@ struct dmt_context {
     std::vector<Ctl> hctl;                 // per-job control blocks read back after the loop
     hipStream_t side = nullptr;            // the 3D loop kernel of a mixed batch runs here
     hipEvent_t fork = nullptr, join = nullptr;
+    // grid iterations of paused jobs of a batch run side by side on these, forked from the
+    // launch stream and joined back into it
+    hipStream_t hand[HAND_STREAMS] = {};
+    hipEvent_t hand_join[HAND_STREAMS] = {};
     unsigned long long ph[3] = {0, 0, 0};  // loop phase ticks of the last correction call
     // kernel timing: event pairs per kernel family, recorded on the launch stream
     bool prof = false;
@@ -661,28 +666,58 @@ dmt_status run_wg(dmt_context* c, std::vector<Job*>& jobs, bool with_log, hipStr
         if (max_it > bound || sum_it == progress)
             return fail(c, DMT_E_HIP, "correction loop exceeded the iteration bound or stopped advancing");
         progress = sum_it;
-        bool any_paused = false;
-        for (int j = 0; j < nj; j++) {
-            if (c->hctl[jobs[j]->slot].done || !c->hctl[jobs[j]->slot].paused) continue;
-            // a large iteration: run a few as full-grid launches, with room in the log for them
-            any_paused = true;
-            const Job* J = jobs[j];
-            FrontierBufs& hj = hb[pos[j]];
-            const int64_t it0 = c->hctl[jobs[j]->slot].it;
-            if (with_log && it0 + grid_batch + 2 > hj.log_cap) {
-                TRY(grow_log(c, (size_t)(it0 + grid_batch) * 2 + 4096, it0, st));
-                hj.log = P<long long>(c->dlog);
-                hj.log_cap = (int)(c->dlog.cap / (sizeof(long long) * DMT_LOG_WORDS));
-                HIPCHK(c, hipMemcpyAsync(P<FrontierBufs>(c->jobs_dev) + pos[j], &hj, sizeof(FrontierBufs),
-                                         hipMemcpyHostToDevice, st));
-            }
-            const bool from_sstep = c->hctl[jobs[j]->slot].paused == 2;
-            HIPCHK(c, hipMemsetAsync(&J->B.ctl->paused, 0, sizeof(int), st));
+        std::vector<int> paused;
+        for (int j = 0; j < nj; j++)
+            if (!c->hctl[jobs[j]->slot].done && c->hctl[jobs[j]->slot].paused) paused.push_back(j);
+        // the paused jobs' grid iterations are independent (each touches its own workspace and
+        // control block): up to HAND_STREAMS of them run at a time
+        if (!paused.empty()) {
             ProfScope ps(c, DMT_PROF_LOOP, st, 0);
-            TRY(J->D == 2 ? grid_iterations<2>(c, hj, J->dm, grid_batch, from_sstep, st)
-                          : grid_iterations<3>(c, hj, J->dm, grid_batch, from_sstep, st));
+            const int ns = (int)std::min<size_t>(HAND_STREAMS, paused.size());
+            if (ns > 1) {
+                if (!c->fork) HIPCHK(c, hipEventCreateWithFlags(&c->fork, hipEventDisableTiming));
+                for (int k = 0; k < ns; k++) {
+                    if (!c->hand[k]) {
+                        HIPCHK(c, hipStreamCreateWithFlags(&c->hand[k], hipStreamNonBlocking));
+                        HIPCHK(c, hipEventCreateWithFlags(&c->hand_join[k], hipEventDisableTiming));
+                    }
+                }
+            }
+            for (int j : paused) {
+                // a large iteration: reset the pause and make room in the log (on st, before the fork)
+                const Job* J = jobs[j];
+                FrontierBufs& hj = hb[pos[j]];
+                const int64_t it0 = c->hctl[jobs[j]->slot].it;
+                if (with_log && it0 + grid_batch + 2 > hj.log_cap) {
+                    TRY(grow_log(c, (size_t)(it0 + grid_batch) * 2 + 4096, it0, st));
+                    hj.log = P<long long>(c->dlog);
+                    hj.log_cap = (int)(c->dlog.cap / (sizeof(long long) * DMT_LOG_WORDS));
+                    HIPCHK(c, hipMemcpyAsync(P<FrontierBufs>(c->jobs_dev) + pos[j], &hj, sizeof(FrontierBufs),
+                                             hipMemcpyHostToDevice, st));
+                }
+                HIPCHK(c, hipMemsetAsync(&J->B.ctl->paused, 0, sizeof(int), st));
+            }
+            if (ns > 1) {
+                HIPCHK(c, hipEventRecord(c->fork, st));
+                for (int k = 0; k < ns; k++) HIPCHK(c, hipStreamWaitEvent(c->hand[k], c->fork, 0));
+            }
+            for (size_t i = 0; i < paused.size(); i++) {
+                // a few iterations as full-grid launches
+                const int j = paused[i];
+                const Job* J = jobs[j];
+                const bool from_sstep = c->hctl[J->slot].paused == 2;
+                hipStream_t hs = ns > 1 ? c->hand[i % ns] : st;
+                TRY(J->D == 2 ? grid_iterations<2>(c, hb[pos[j]], J->dm, grid_batch, from_sstep, hs)
+                              : grid_iterations<3>(c, hb[pos[j]], J->dm, grid_batch, from_sstep, hs));
+            }
+            if (ns > 1) {
+                for (int k = 0; k < ns; k++) {
+                    HIPCHK(c, hipEventRecord(c->hand_join[k], c->hand[k]));
+                    HIPCHK(c, hipStreamWaitEvent(st, c->hand_join[k], 0));
+                }
+            }
+            continue;
         }
-        if (any_paused) continue;
         if (!log_full) continue;
         // the log is full (a single job): grow it, point the job at it and resume
         const int64_t host_it = c->hctl[jobs[0]->slot].it;
@@ -1104,6 +1139,10 @@ dmt_status dmt_context_destroy(dmt_context* c) {
     if (c->fork) (void)hipEventDestroy(c->fork);
     if (c->join) (void)hipEventDestroy(c->join);
     if (c->side) (void)hipStreamDestroy(c->side);
+    for (int k = 0; k < HAND_STREAMS; k++) {
+        if (c->hand_join[k]) (void)hipEventDestroy(c->hand_join[k]);
+        if (c->hand[k]) (void)hipStreamDestroy(c->hand[k]);
+    }
     if (c->hcnt) (void)hipHostFree(c->hcnt);
     if (c->hscratch) (void)hipHostFree(c->hscratch);
     delete c;
