@@ -103,7 +103,8 @@ typedef struct {
  * (troublemaker branches fixed), n_req (vertices requested), changed (vertices edited), then
  * the work of the frontier forms in that iteration (0 in the dense form): dirty vertices,
  * affected anchors, listed violating anchors, branches whose first differing cell was
- * settled, branch cells examined while settling them, branch cells touched, and the duration
+ * settled, branch cells examined while settling them, branch cells touched (on dirty vertices
+ * whose own or top-cell pairing changed), and the duration
  * of the iteration in the resident loop in 10 ns ticks (0 elsewhere; timing, not a result). */
 #define DMT_LOG_WORDS 20
 

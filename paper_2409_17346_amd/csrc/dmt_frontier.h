@@ -29,7 +29,7 @@ namespace dmt {
 struct Slot {
     unsigned long long cnt[CNT_WORDS];  // log record layout
     int n_dv, n_da, n_vl;   // dirty vertices, affected anchors, violation list of this iteration
-    int n_tc;               // branch cells of f on a dirty vertex (touched this iteration)
+    int n_tc;               // branch cells of f on a dirty vertex whose codes changed (touched)
     int n_db;               // branches with a touched cell
     int n_scan;             // branch cells examined to settle those branches
 };
@@ -469,26 +469,25 @@ __device__ __forceinline__ void phase_grad(const FrontierView& B, const Dims& dm
     Slot& S = slot_of<WG>(B, it);
     const int n = ld_relaxed(&S.n_dv);
     const int* list = B.dvl[it & 1];
+    // With branch tracking, the branch cells on each dirty vertex whose vertex or top-cell codes
+    // changed are listed as touched (each dirty vertex is listed once per iteration, so each cell
+    // appears at most D + 1 times).  A cell's code is written only by the vertex whose lower star
+    // holds it, which is one of the cell's vertices: a changed cell is always listed.
+    const bool track = B.vstart != nullptr;
     for (int base = 0; base < n; base += gsize) {
         if (wave_done(base, gtid, n)) break;
         const int i = base + gtid;
-        if (i >= n) continue;
-        const int t = list[i];
-        grad_vertex<D>(t, gcur, B.gpl, dm);
-        gnext[t] = gcur[t];
-    }
-    // the branch cells on the dirty vertices (each dirty vertex is listed once per iteration, so
-    // each cell appears at most D + 1 times)
-    if (B.vstart) {
-        for (int base = 0; base < n; base += gsize) {
-            if (wave_done(base, gtid, n)) break;
-            const int i0 = base + gtid;
-            int e0 = 0, e1 = 0;
-            if (i0 < n) {
-                const int t = list[i0];
+        int e0 = 0, e1 = 0;
+        if (i < n) {
+            const int t = list[i];
+            const bool ch = grad_vertex<D, true>(t, gcur, B.gpl, dm);
+            gnext[t] = gcur[t];
+            if (track && ch) {
                 e0 = B.vstart[t];
                 e1 = B.vstart[t + 1];
             }
+        }
+        if (track) {
             int pos = wave_append_n(e1 - e0, &S.n_tc);
             for (int e = e0; e < e1; e++) B.tcl[pos++] = B.ecell[e];
         }

@@ -235,8 +235,10 @@ __device__ __forceinline__ int anchor_at(int v, const Dims& dm) {
     }
 }
 
-template <int D>
-__device__ __forceinline__ void grad_vertex(const int v, const float* __restrict__ h, uint8_t* __restrict__ planes,
+// With TRACK, returns whether the code of v or of a top cell of v's lower star changed (the
+// cells a discrete gradient path can run through); otherwise false.
+template <int D, bool TRACK = false>
+__device__ __forceinline__ bool grad_vertex(const int v, const float* __restrict__ h, uint8_t* __restrict__ planes,
                                             const Dims& dm) {
     constexpr int NS = Geom<D>::NS;
     constexpr int FULL = Geom<D>::FULL;
@@ -280,6 +282,8 @@ __device__ __forceinline__ void grad_vertex(const int v, const float* __restrict
         constexpr int s = decltype(sc)::value;
         if (((L >> s) & 1) && below[s] == 0) { m = s; vcode = CODE_UP | C27Rel<D, s, -1>::value; }
     });
+    bool changed = false;
+    if constexpr (TRACK) changed = planes[v] != vcode;
     planes[v] = vcode;
 
     // edges (v, s)
@@ -332,7 +336,9 @@ __device__ __forceinline__ void grad_vertex(const int v, const float* __restrict
                 });
             }
         }
-        planes[(size_t)G<D>::g.tri_plane[i] * dm.n + anchor_at<D, as>(v, dm)] = code;
+        uint8_t* const dst = &planes[(size_t)G<D>::g.tri_plane[i] * dm.n + anchor_at<D, as>(v, dm)];
+        if constexpr (TRACK && D == 2) changed |= *dst != code;
+        *dst = code;
     });
 
     // tetrahedra (v, s, t, u)
@@ -350,9 +356,12 @@ __device__ __forceinline__ void grad_vertex(const int v, const float* __restrict
             else if (t_s && !u_t) { low = t; tm = tmin[G<D>::g.tri_index[s][u]]; downc = CODE_DOWN | C27Rel<D, t, as>::value; }
             else { low = s; tm = tmin[G<D>::g.tri_index[t][u]]; downc = CODE_DOWN | C27Rel<D, s, as>::value; }
             const uint8_t code = (tm == low) ? downc : CODE_CRIT;
-            planes[(size_t)G<D>::g.tet_plane[i] * dm.n + anchor_at<D, as>(v, dm)] = code;
+            uint8_t* const dst = &planes[(size_t)G<D>::g.tet_plane[i] * dm.n + anchor_at<D, as>(v, dm)];
+            if constexpr (TRACK) changed |= *dst != code;
+            *dst = code;
         });
     }
+    return changed;
 }
 
 template <int D>
