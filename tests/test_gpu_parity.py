@@ -268,6 +268,25 @@ def test_correct_batch_matches_oracle_and_single(ctx, dmt, tier):
         assert torch.equal(s.g.view(torch.int32), r.g.view(torch.int32)) and torch.equal(s.q, r.q)
 
 
+def test_correct_batch_concurrent_handoff(ctx, dmt, monkeypatch):
+    """With a low hand-off limit several jobs of a batch pause together and run their full-grid
+    iterations side by side on separate streams: every job still equals the oracle."""
+    monkeypatch.setenv("DMT_WG_MAX_ANCHORS", "16")
+    monkeypatch.setenv("DMT_GRID_BATCH", "2")
+    ws = _batch_jobs()
+    fields = [(_t(w.f), _t(w.g_hat), w.xi) for w in ws]
+    res = dmt.dmt_correct_batch(ctx, fields, tier=4, q_max=6)
+    for w, r in zip(ws, res):
+        nx, ny, nz = w.dims
+        o = oracle.correct(oracle.Complex.grid(nx, ny, nz), w.f.reshape(-1), w.g_hat.reshape(-1), w.xi, 4, 6)
+        assert r.status == o["status"], w.name
+        for k, v in o["stats"].items():
+            if k != "status":
+                assert r.stats[k] == v, (w.name, k)
+        assert np.array_equal(r.g.cpu().numpy().reshape(-1).view(np.uint32), o["g"].view(np.uint32)), w.name
+        assert np.array_equal(r.q.cpu().numpy().reshape(-1), o["q"]), w.name
+
+
 def test_correct_batch_isolates_bad_jobs(ctx, dmt):
     good = synth.tiny_cases(3, (20, 18), rel=0.1, kind="uniform")
     bad = synth.tiny_cases(4, (9, 9), rel=0.1, kind="uniform")
