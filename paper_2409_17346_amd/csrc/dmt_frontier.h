@@ -342,17 +342,27 @@ __device__ __forceinline__ void request_apply(const FrontierView& B, const Dims&
 
 // ---- violation mask of one anchor: planes whose criticality differs between f and g --------
 
-template <int D, int P>
-__device__ __forceinline__ void vmask_plane(const Dims& dm, int a, int x, int y, int z, const uint8_t* fpl,
-                                            const uint8_t* gpl, int tier, uint32_t& m) {
-    constexpr auto& g = G<D>::g;
-    constexpr int dim = g.bdim[P];
-    if (!(tier == 1 && dim != 0 && dim != D) && cell_exists<D, P>(dm, x, y, z)) {
-        const bool fc = fpl[(size_t)P * dm.n + a] == CODE_CRIT;
-        const bool gc = gpl[(size_t)P * dm.n + a] == CODE_CRIT;
-        if (fc != gc) m |= 1u << P;
-    }
-    if constexpr (P + 1 < Geom<D>::NB) vmask_plane<D, P + 1>(dm, a, x, y, z, fpl, gpl, tier, m);
+// Every plane's codes are loaded unconditionally (plane P of anchor a is in bounds for every
+// anchor), so all loads are in flight together; planes whose cell does not exist, or that the
+// tier ignores, are masked afterwards.
+template <int D>
+__device__ __forceinline__ uint32_t vmask_anchor(const Dims& dm, int a, int x, int y, int z,
+                                                 const uint8_t* __restrict__ fpl, const uint8_t* __restrict__ gpl,
+                                                 int tier) {
+    uint8_t fc[Geom<D>::NB], gc[Geom<D>::NB];
+    static_for<0, Geom<D>::NB>([&](auto pc) {
+        constexpr int P = decltype(pc)::value;
+        fc[P] = fpl[(size_t)P * dm.n + a];
+        gc[P] = gpl[(size_t)P * dm.n + a];
+    });
+    uint32_t m = 0;
+    static_for<0, Geom<D>::NB>([&](auto pc) {
+        constexpr int P = decltype(pc)::value;
+        constexpr int dim = G<D>::g.bdim[P];
+        const bool use = !(tier == 1 && dim != 0 && dim != D) && cell_exists<D, P>(dm, x, y, z);
+        m |= (uint32_t)(use && ((fc[P] == CODE_CRIT) != (gc[P] == CODE_CRIT))) << P;
+    });
+    return m;
 }
 
 // ---- target of one violating plane (Rules A and B, as classify_plane) ---------------------
@@ -616,7 +626,7 @@ __device__ __forceinline__ void phase_vr(const FrontierView& B, const Dims& dm, 
             a = it == 0 ? i0 : alist[i0];
             int x, y, z;
             coords(dm, a, x, y, z);
-            vmask_plane<D, 0>(dm, a, x, y, z, B.fpl, B.gpl, B.tier, m);
+            m = vmask_anchor<D>(dm, a, x, y, z, B.fpl, B.gpl, B.tier);
             B.vmask[a] = m;
         } else if (i0 < ntot) {
             a = vlist[i0 - na];
