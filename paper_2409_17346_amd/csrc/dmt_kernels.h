@@ -247,12 +247,13 @@ __device__ __forceinline__ bool grad_vertex(const int v, const float* __restrict
     coords(dm, v, x, y, z);
     const float hv = h[v];
     float hn[NS];
-    uint32_t L = 0;
+    uint32_t L = 0, inside = 0;
     static_for<0, NS>([&](auto sc) {
         constexpr int s = decltype(sc)::value;
         constexpr int dx = G<D>::g.slot_d[s][0], dy = G<D>::g.slot_d[s][1], dz = G<D>::g.slot_d[s][2];
         const bool ok = (unsigned)(x + dx) < (unsigned)dm.nx && (unsigned)(y + dy) < (unsigned)dm.ny &&
                         (unsigned)(z + dz) < (unsigned)dm.nz;
+        inside |= (uint32_t)ok << s;
         // unconditional load (a neighbour outside the grid reads v itself) so that all loads are
         // issued together; its value is then replaced by 0 and never used (L excludes it)
         const float hs = h[ok ? v + dx + dm.nx * dy + dm.nxy * dz : v];
@@ -261,6 +262,21 @@ __device__ __forceinline__ bool grad_vertex(const int v, const float* __restrict
         const bool lw = s < FULL ? (hn[s] <= hv) : (hn[s] < hv);
         L |= (uint32_t)(ok && lw) << s;
     });
+    // 2D with TRACK: the old codes of v and of its triangles are loaded here, beside the
+    // neighbour values, rather than just before each store (where every load would wait for the
+    // stores before it); a triangle outside the grid reads v's own entry, never used
+    uint8_t old_v = 0;
+    uint8_t old_t[NTRI];
+    if constexpr (TRACK && D == 2) {
+        old_v = planes[v];
+        static_for<0, NTRI>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            constexpr int s = G<D>::g.tri_s[i], t = G<D>::g.tri_t[i];
+            constexpr int as = G<D>::g.tri_anchor_slot[i];
+            const bool ex = ((inside >> s) & 1) && ((inside >> t) & 1);
+            old_t[i] = planes[ex ? (size_t)G<D>::g.tri_plane[i] * dm.n + anchor_at<D, as>(v, dm) : (size_t)v];
+        });
+    }
     // below[s] = lower neighbours that precede neighbour s (slot order = id order)
     uint32_t below[NS];
     static_for<0, NS>([&](auto sc) { below[decltype(sc)::value] = 0; });
@@ -283,7 +299,7 @@ __device__ __forceinline__ bool grad_vertex(const int v, const float* __restrict
         if (((L >> s) & 1) && below[s] == 0) { m = s; vcode = CODE_UP | C27Rel<D, s, -1>::value; }
     });
     bool changed = false;
-    if constexpr (TRACK) changed = planes[v] != vcode;
+    if constexpr (TRACK) changed = (D == 2 ? old_v : planes[v]) != vcode;
     planes[v] = vcode;
 
     // edges (v, s)
@@ -337,7 +353,7 @@ __device__ __forceinline__ bool grad_vertex(const int v, const float* __restrict
             }
         }
         uint8_t* const dst = &planes[(size_t)G<D>::g.tri_plane[i] * dm.n + anchor_at<D, as>(v, dm)];
-        if constexpr (TRACK && D == 2) changed |= *dst != code;
+        if constexpr (TRACK && D == 2) changed |= old_t[i] != code;
         *dst = code;
     });
 
