@@ -68,6 +68,8 @@ def lib():
     L.oracle_correct.argtypes = [C.c_void_p, PF, PF, C.c_float, C.c_int, C.c_int, C.c_int64,
                                  PF, P8, P64, P64, C.c_int64]
     L.oracle_decode.argtypes = [PF, P8, C.c_int64, P64, PF, C.c_int64, C.c_float, C.c_int, PF]
+    L.oracle_residual.restype = C.c_int64
+    L.oracle_residual.argtypes = [C.c_void_p, PF, PF, C.c_int, P64, P64, C.c_int64]
     _lib = L
     return L
 
@@ -204,6 +206,21 @@ def correct(cx: Complex, f, g_hat, xi: float, tier: int = 4, q_max: int = 6, max
         out.update(g=g, q=q, lossless_idx=idx, lossless_val=g[idx].copy(),
                    log=log[:min(st["iterations"], log_cap)].copy())
     return out
+
+
+def residual(cx: Complex, f, g, tier: int = 4):
+    """Violations of g against f (what the correction loop would fix next): an int64 array of
+    (dimension, cell id) rows -- cells whose criticality differs, else at tier >= 3 the first
+    differing cell of each checked separatrix branch."""
+    f = _f32(f)
+    g = _f32(g)
+    L = lib()
+    z = np.zeros(1, dtype=np.int64)
+    n = L.oracle_residual(cx.h, _p(f, PF), _p(g, PF), tier, _p(z, P64), _p(z, P64), 0)
+    dims = np.zeros(max(n, 1), dtype=np.int64)
+    ids = np.zeros(max(n, 1), dtype=np.int64)
+    L.oracle_residual(cx.h, _p(f, PF), _p(g, PF), tier, _p(dims, P64), _p(ids, P64), n)
+    return np.stack([dims[:n], ids[:n]], axis=1)
 
 
 def decode(g_hat, q, lossless_idx, lossless_val, xi: float, q_max: int):

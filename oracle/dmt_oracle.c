@@ -520,7 +520,7 @@ static int32_t pair_apex(const ocx *cx, const grad_t *G, int d, int64_t c, int *
  *    sigma in f too, sigma is paired in f, and the apex of sigma's f-pair is lowered so that
  *    sigma returns to its f-partner.
  * Marks targets in st->req; adds counts to cnt[2d] (FP) and cnt[2d+1] (FN); returns total. */
-static int64_t c_detect(state_t *st, const grad_t *F, const grad_t *G, int tier, int64_t *cnt) {
+static int64_t c_detect(state_t *st, const grad_t *F, const grad_t *G, int tier, int64_t *cnt, vec *where) {
     const ocx *cx = st->cx;
     int n = cx->top;
     int64_t total = 0;
@@ -551,6 +551,7 @@ static int64_t c_detect(state_t *st, const grad_t *F, const grad_t *G, int tier,
                 cnt[2 * d + 1]++;
             }
             st->req[target] = 1;
+            if (where) { vpush(where, d); vpush(where, c); }
             total++;
         }
     }
@@ -565,7 +566,7 @@ static int64_t c_detect(state_t *st, const grad_t *F, const grad_t *G, int tier,
  * Reading: the first divergence along f's branch is where tracing the same separatrix in g
  * leaves it, so g's separatrices need not be extracted separately. */
 static int64_t s_detect(state_t *st, const grad_t *F, const grad_t *G, const omsc *mf, int tier,
-                        int64_t *tm_desc, int64_t *tm_asc) {
+                        int64_t *tm_desc, int64_t *tm_asc, vec *where) {
     const ocx *cx = st->cx;
     int n = cx->top;
     int64_t total = 0;
@@ -578,6 +579,7 @@ static int64_t s_detect(state_t *st, const grad_t *F, const grad_t *G, const oms
             if (ok) {
                 int lo_d; int64_t lo_id;
                 st->req[pair_apex(cx, F, 0, v, &lo_d, &lo_id)] = 1;
+                if (where) { vpush(where, 0); vpush(where, v); }
                 (*tm_desc)++;
                 total++;
             }
@@ -593,6 +595,7 @@ static int64_t s_detect(state_t *st, const grad_t *F, const grad_t *G, const oms
             if (ok) {
                 int lo_d; int64_t lo_id;
                 st->req[pair_apex(cx, F, n, T, &lo_d, &lo_id)] = 1;
+                if (where) { vpush(where, n); vpush(where, T); }
                 (*tm_asc)++;
                 total++;
             }
@@ -672,10 +675,10 @@ int oracle_correct(const ocx *cx, const float *f, const float *g_hat, float xi, 
     for (;;) {
         oracle_gradient(cx, st.g, G.up, G.down);
         int64_t rec[16] = {0};
-        int64_t viol = c_detect(&st, &F, &G, tier, rec + 1);
+        int64_t viol = c_detect(&st, &F, &G, tier, rec + 1, NULL);
         int kind = 1;
         if (viol == 0 && tier >= 3) {
-            viol = s_detect(&st, &F, &G, mf, tier, rec + 9, rec + 10);
+            viol = s_detect(&st, &F, &G, mf, tier, rec + 9, rec + 10, NULL);
             kind = 2;
         }
         if (viol == 0) { converged = 1; break; }
@@ -711,4 +714,35 @@ int oracle_correct(const ocx *cx, const float *f, const float *g_hat, float xi, 
     grad_free(&G);
     free(st.g); free(st.lo); free(st.q); free(st.floored); free(st.req);
     return (int)stats[9];
+}
+
+/* The violations of g against f that the correction loop would see at this state: the cells
+ * whose criticality differs (Section 4.3), or, when there are none and tier >= 3, the first
+ * differing cell of every separatrix branch that the tier checks (Section 4.4), one entry per
+ * branch.  Writes up to cap (dimension, cell id) pairs; returns the total count. */
+int64_t oracle_residual(const ocx *cx, const float *f, const float *g, int tier, int64_t *dims, int64_t *ids,
+                        int64_t cap) {
+    int64_t nv = cx->nv;
+    state_t st = {0};
+    st.cx = cx; st.f = f; st.ghat = g; st.g = (float *)g;
+    st.req = xcalloc((size_t)nv, 1);
+    grad_t F, G;
+    grad_alloc(cx, &F);
+    grad_alloc(cx, &G);
+    oracle_gradient(cx, f, F.up, F.down);
+    oracle_gradient(cx, g, G.up, G.down);
+    vec where = {0};
+    int64_t cnt[16] = {0};
+    int64_t viol = c_detect(&st, &F, &G, tier, cnt + 1, &where);
+    if (viol == 0 && tier >= 3) {
+        omsc *mf = msc_from_grad(cx, &F);
+        viol = s_detect(&st, &F, &G, mf, tier, cnt + 9, cnt + 10, &where);
+        omsc_free(mf);
+    }
+    for (int64_t k = 0; k < viol && k < cap; k++) { dims[k] = where.p[2 * k]; ids[k] = where.p[2 * k + 1]; }
+    free(where.p);
+    free(st.req);
+    grad_free(&F);
+    grad_free(&G);
+    return viol;
 }

@@ -71,6 +71,12 @@ int oracle_correct(const ocx *cx, const float *f, const float *g_hat, float xi, 
                    int q_max, int64_t max_iters, float *g_out, uint8_t *q_out, int64_t *stats,
                    int64_t *log, int64_t log_cap);
 
+/* Violations of g against f as the correction loop sees them: cells whose criticality differs,
+ * else (tier >= 3) the first differing cell of each separatrix branch the tier checks.  Writes
+ * up to cap (dimension, id) pairs and returns the total. */
+int64_t oracle_residual(const ocx *cx, const float *f, const float *g, int tier, int64_t *dims, int64_t *ids,
+                        int64_t cap);
+
 /* Decoder: g = lossless ? stored value : (g_hat - q*Delta) rounded once, Delta = xi*2^-q_max. */
 void oracle_decode(const float *g_hat, const uint8_t *q, int64_t n, const int64_t *idx,
                    const float *val, int64_t n_lossless, float xi, int q_max, float *g_out);

@@ -19,6 +19,8 @@ import oracle
 from oracle import brute
 from paper_2409_17346_amd import synth
 
+from floorcheck import collision_field, explained
+
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
 
@@ -144,6 +146,23 @@ def test_msc_matches_brute_force(shape, kind):
                 (w,) = tuple(b["pair"][cur] - cur)
                 cur = frozenset([w])
             assert m.min_label[v] == min(cur)
+        # max labels: terminal of every top cell's own ascending V-path (BOUNDARY = -1); ids of
+        # top cells that leave the grid read -2
+        top = cx.top
+        ids = {frozenset(cx.vertices(top, t)): t for t in range(cx.ncell[top]) if cx.vertices(top, t)}
+        _, _, cof = brute.gradient(cells, h)
+        assert len(m.max_label) == cx.ncell[top]
+        for t in range(cx.ncell[top]):
+            vs = cx.vertices(top, t)
+            if vs is None:
+                assert m.max_label[t] == -2
+                continue
+            T = frozenset(vs)
+            term = T
+            while term is not None and term in b["pair"]:
+                others = [c for c in cof[b["pair"][term]] if c != term]
+                term = others[0] if others else None
+            assert m.max_label[t] == (-1 if term is None else ids[term]), (t, vs)
 
 
 # ------------------------------------------------------------------------------------------
@@ -246,6 +265,16 @@ def _exact_within(f, g, xi):
         assert abs(Fraction(float(a)) - Fraction(float(b))) <= Fraction(float(xi))
 
 
+def _assert_floor_collision_stall(cx, dims, f, g, xi, tier, n_residual):
+    """Every violation left at a stall has an equal-floor inverted pair of floored vertices in the
+    closed 1-ring of its highest vertex (the only way decrease-only edits can get stuck)."""
+    res = oracle.residual(cx, f, g, tier)
+    assert len(res) == n_residual
+    lo, _ = oracle.bounds(f, xi)
+    ok = explained(dims, f, g, lo, res)
+    assert ok.all(), res[~ok][:8]
+
+
 def _cases():
     out = []
     for shape in [(8, 8), (12, 9), (5, 5, 4)]:
@@ -280,6 +309,7 @@ def test_correction_postconditions(shape, kind, ghat, seed):
         assert st["n_edited"] == st["n_quantized"] + st["n_lossless"]
         if r["status"] != "ok":
             assert st["stalled"] == 1 and st["residual_violations"] > 0
+            _assert_floor_collision_stall(cx, w.dims, f, g, w.xi, tier, st["residual_violations"])
             continue
         bg = brute.msc(cells, g)
         n = cx.top
@@ -397,16 +427,20 @@ def test_first_step_targets_follow_paper_cases(top):
     assert checked > 10
 
 
-def test_troublemaker_targets_follow_paper():
-    """S-loop targets (Section 4.4): a vertex i paired with ik in g but ij in f -> lower j; a top
-    cell paired with a different facet in g than in f -> lower the vertex its f-facet lacks."""
+@pytest.mark.parametrize("dims", [(7, 6, 1), (5, 5, 4)])
+def test_troublemaker_targets_follow_paper(dims):
+    """S-loop targets (Section 4.4): a vertex i paired with ik in g but ij in f -> lower j (0-dim
+    troublemaker); a top cell paired with a different facet in g than in f -> lower the vertex its
+    f-facet lacks (2D: triangle ijk paired with edge ij in f; 3D, TM2: triangle ijk paired with
+    ijkl in f but ijkq in g -> lower l)."""
     rng = np.random.default_rng(11)
-    nx, ny = 7, 6
-    cx = oracle.Complex.grid(nx, ny, 1)
-    cells = brute.kuhn_complex((nx, ny))
+    nx, ny, nz = dims
+    shape = (ny, nx) if nz == 1 else (nz, ny, nx)
+    cx = oracle.Complex.grid(nx, ny, nz)
+    cells = brute.kuhn_complex((nx, ny) if nz == 1 else (nx, ny, nz))
     found = 0
     for trial in range(60):
-        f = synth.random_field((ny, nx), "smooth", trial).reshape(-1)
+        f = synth.random_field(shape, "smooth", trial).reshape(-1)
         xi = float(np.float32(0.15 * (f.max() - f.min())))
         gh = synth.uniform_noise(f, xi, rng)
         r0 = oracle.correct(cx, f, gh, xi, 4, 6)
@@ -438,3 +472,106 @@ def test_troublemaker_targets_follow_paper():
         assert R and R <= allowed
         found += 1
     assert found >= 3
+
+
+def _brute_residual(cells, f, g, tier):
+    """Violating cells from the brute force: criticality differences (tier filter), else the first
+    differing cell of each separatrix branch (tier 3: only branches whose g-path ends elsewhere)."""
+    n = len(cells) - 1
+    pf, critf, cof = brute.gradient(cells, f)
+    pg, critg, _ = brute.gradient(cells, g)
+    out = [c for d in range(n + 1) if not (tier == 1 and d not in (0, n))
+           for c in cells[d] if (c in critf[d]) != (c in critg[d])]
+    if out or tier < 3:
+        return out
+
+    def end_desc(v):
+        cur = frozenset([v])
+        while cur in pg:
+            (w,) = tuple(pg[cur] - cur)
+            cur = frozenset([w])
+        return min(cur)
+
+    def end_asc(T):
+        while T in pg:
+            others = [x for x in cof[pg[T]] if x != T]
+            if not others:
+                return None
+            T = others[0]
+        return T
+
+    bf = brute.msc(cells, f)
+    for _, seq in sorted(bf["desc"], key=lambda x: (sorted(x[0]), x[1])):
+        for v in seq:
+            c = frozenset([v])
+            if pf.get(c) != pg.get(c):
+                if tier == 4 or end_desc(seq[0]) != seq[-1]:
+                    out.append(c)
+                break
+    for _, seq, t in bf["asc"]:
+        for T in seq:
+            if pf.get(T) != pg.get(T):
+                if tier == 4 or end_asc(seq[0]) != t:
+                    out.append(T)
+                break
+    return out
+
+
+@pytest.mark.parametrize("dims", [(6, 5, 1), (4, 4, 3)])
+def test_residual_list_matches_brute_force(dims):
+    """oracle.residual lists the violations the loop would fix: checked as a multiset of cells
+    against the brute force on g_hat and on partly corrected fields, at every tier."""
+    nx, ny, nz = dims
+    shape = (ny, nx) if nz == 1 else (nz, ny, nx)
+    cx = oracle.Complex.grid(nx, ny, nz)
+    cells = brute.kuhn_complex((nx, ny) if nz == 1 else (nx, ny, nz))
+    checked = 0
+    for seed in range(8):
+        w = synth.tiny_cases(seed, shape, rel=0.2, kind="smooth", ghat="noise")
+        f, gh = w.f.reshape(-1), w.g_hat.reshape(-1)
+        for tier in (1, 2, 3, 4):
+            for k in (0, 2, 5):
+                g = oracle.correct(cx, f, gh, w.xi, tier, 6, max_iters=k)["g"]
+                res = oracle.residual(cx, f, g, tier)
+                mine = sorted(tuple(sorted(cx.vertices(int(d), int(i)))) for d, i in res)
+                ref = sorted(tuple(sorted(c)) for c in _brute_residual(cells, f, g, tier))
+                assert mine == ref
+                checked += len(ref) > 0
+    assert checked > 20
+
+
+@pytest.mark.parametrize("dims", [(6, 6, 1), (8, 7, 1), (4, 4, 4), (5, 4, 3)])
+def test_stalls_are_floor_collisions(dims):
+    """Fields built so that many floors collide (xi = 1, most values below 2^-24) stall; every
+    violation left behind is explained by an equal-floor inverted pair at the floors, and the
+    violations reported match the oracle's residual count."""
+    nx, ny, nz = dims
+    shape = (ny, nx) if nz == 1 else (nz, ny, nx)
+    cx = oracle.Complex.grid(nx, ny, nz)
+    stalls = 0
+    for seed in range(12):
+        f, rng = collision_field(shape, seed)
+        gh = synth.uniform_noise(f, 1.0, rng)
+        f, gh = f.reshape(-1), gh.reshape(-1)
+        for tier in (1, 2, 4):
+            r = oracle.correct(cx, f, gh, 1.0, tier, 6)
+            if r["status"] == "ok":
+                continue
+            assert r["stats"]["stalled"] == 1
+            _assert_floor_collision_stall(cx, (nx, ny, nz), f, r["g"], 1.0, tier,
+                                          r["stats"]["residual_violations"])
+            stalls += 1
+    assert stalls >= 6
+
+
+def test_floor_collision_check_rejects_other_stalls():
+    """The stall check is not vacuous: without floor collisions (distinct, well separated floors)
+    an unexplained violation is reported as such."""
+    nx, ny = 6, 5
+    cx = oracle.Complex.grid(nx, ny, 1)
+    f = synth.random_field((ny, nx), "perm", 3).reshape(-1)       # integers, floors never collide
+    gh = f[::-1].copy()                                          # every order reversed
+    res = oracle.residual(cx, f, gh, 2)
+    assert len(res) > 0
+    lo, _ = oracle.bounds(f, 100.0)
+    assert not explained((nx, ny, 1), f, gh, lo, res).any()
