@@ -234,6 +234,28 @@ dmt_status dmt_server_submit(dmt_server *srv, const dmt_job *job, int64_t *ticke
  * The lossless edits are the vertices with q_out == 0xFF, with values g_out.  Thread-safe. */
 dmt_status dmt_server_poll(dmt_server *srv, int64_t ticket, int32_t wait, dmt_job *result);
 
+/* Accounting of a server (host values; any pointer may be NULL): inflight_bytes = the bytes
+ * admission counts (each job in flight at the larger of its estimate and the workspace it holds,
+ * each idle slot at the workspace it still holds, plus the shared buffers), held_bytes = device
+ * bytes held by the server's workspaces when last accounted, free_slots / pending = idle slots and
+ * queued jobs, distinct_free_slots = idle slots counted once each (equal to free_slots unless
+ * the slot list is corrupt).  The workspace of a finished job is kept for reuse; admission
+ * releases idle slots' workspaces when a job would not fit the budget otherwise.
+ * Setting DMT_FAULT_OUTPUTS=k in the environment before dmt_server_create makes the output step
+ * of the k-th finished job fail with DMT_E_NOMEM (a test of the server's error path).
+ * Thread-safe. */
+dmt_status dmt_server_info(dmt_server *srv, int64_t *inflight_bytes, int64_t *held_bytes, int32_t *free_slots,
+                           int32_t *pending, int32_t *distinct_free_slots);
+
+/* Lossless edits of a finished batch or served job, read from its outputs (Section 4.7: the
+ * vertices whose edit is stored as a value): the vertex ids with q_out == 0xFF in ascending
+ * order and their values g_out.  n = vertices.  count_host receives the number of entries; with
+ * cap == 0 nothing else is written, otherwise cap must be >= that count (else DMT_E_INVALID).
+ * idx_out and val_out are device arrays of cap entries. */
+dmt_status dmt_lossless_list(dmt_context *ctx, const uint8_t *q_out, const float *g_out, int64_t n,
+                             int64_t *idx_out, float *val_out, int64_t cap, int64_t *count_host,
+                             hipStream_t stream);
+
 /* Lossless edits of the last dmt_correct: vertex ids ascending and their final values.
  * Writes min(count, cap) entries, returns the full count in count_host. */
 dmt_status dmt_lossless_edits(dmt_context *ctx, int64_t *idx_out, float *val_out, int64_t cap,

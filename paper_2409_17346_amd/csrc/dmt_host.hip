@@ -590,7 +590,7 @@ dmt_status run_wg(dmt_context* c, std::vector<Job*>& jobs, bool with_log, hipStr
     if (with_log) TRY(grow_log(c, 4096, 0, st));
     const int cap0 = with_log ? (int)(c->dlog.cap / (sizeof(long long) * DMT_LOG_WORDS)) : 0;
     // Every iteration that does not end a job edits at least one vertex, and a vertex takes at
-    // most q_max + 1 edits (Section 4.6), so no job runs more than n (q_max + 1) + 1 iterations.
+    // most q_max + 1 edits (Section 4.5), so no job runs more than n (q_max + 1) + 1 iterations.
     int64_t bound = 0;
     for (int k = 0; k < nj; k++) {
         const Job* J = jobs[order[k]];
@@ -982,6 +982,21 @@ int64_t workspace_estimate(int D, int64_t n) {
     return (D == 2 ? 112 : 224) * n + (1 << 20);
 }
 
+// Device bytes a workspace holds now.
+int64_t held_bytes(JobWs& w) {
+    int64_t s = 0;
+    for (DevBuf* b : w.all()) s += (int64_t)b->cap;
+    return s;
+}
+
+void release(JobWs& w) {
+    for (DevBuf* b : w.all()) {
+        if (b->p) (void)hipFree(b->p);
+        *b = DevBuf{};
+    }
+    w.msc.valid = false;
+}
+
 struct Ticket {
     dmt_job job{};
     Job J;
@@ -1004,22 +1019,53 @@ struct dmt_server {
     std::deque<int64_t> pending;
     std::vector<int> free_slots;
     int64_t next_ticket = 1;
+    // HBM accounting: charge[slot] = bytes the slot is counted for (an active job: the larger of
+    // its estimate and what its workspace holds; an idle slot: what its workspace still holds);
+    // inflight = sum of the charges plus the context's shared buffers
+    std::vector<int64_t> charge;
+    std::vector<int64_t> held;      // bytes each slot's workspace held when last accounted
+    int64_t shared = 0;
     int64_t inflight = 0;
+    int64_t fail_outputs_at = -1;   // fault injection for tests: the k-th finished job's outputs fail
+    int64_t finished = 0;
 };
 
 namespace {
 
+int64_t shared_bytes(dmt_context* c) {
+    int64_t s = 0;
+    for (DevBuf* b : {&c->gpl, &c->req, &c->cnt, &c->flags, &c->part, &c->blk, &c->blkoff, &c->ll_idx, &c->ll_val,
+                      &c->dlog, &c->jobs_dev, &c->ctl_all, &c->queue, &c->scan_tsum, &c->scan_toff})
+        s += (int64_t)b->cap;
+    return s;
+}
+
+// Recomputes inflight from the charges (caller holds s->mu).
+void recount(dmt_server* s) {
+    int64_t t = s->shared;
+    for (int64_t b : s->charge) t += b;
+    s->inflight = t;
+}
+
+// Ends a ticket that is no longer in any worker list.  The slot keeps its workspace for the next
+// job; its charge drops to what the workspace holds.
 void server_finish(dmt_server* s, Ticket& t, dmt_status status) {
+    const int64_t held = held_bytes(s->c->ws[t.J.slot]);
     std::lock_guard<std::mutex> lk(s->mu);
     t.job.status = status;
     t.job.stats = t.J.stats;
     t.state = 2;
-    s->inflight -= t.bytes;
+    s->charge[t.J.slot] = held;
+    s->held[t.J.slot] = held;
+    s->shared = shared_bytes(s->c);
+    recount(s);
     s->free_slots.push_back(t.J.slot);
     s->cv_done.notify_all();
 }
 
-// Setup, f's gradient and branches, frontier state and iteration 0 of newly admitted jobs.
+// Setup, f's gradient and branches, frontier state and iteration 0 of newly admitted jobs.  Each
+// ticket leaves `admit` when it is finished (validation failure) or moved to `active`; on an
+// error the tickets still in `admit` have not been finished.
 dmt_status server_admit(dmt_server* s, std::vector<Ticket*>& admit, std::vector<Ticket*>& active) {
     dmt_context* c = s->c;
     const hipStream_t st = s->st;
@@ -1033,37 +1079,85 @@ dmt_status server_admit(dmt_server* s, std::vector<Ticket*>& admit, std::vector<
     std::vector<unsigned> fl(s->max_jobs + 1);
     HIPCHK(c, hipMemcpyAsync(fl.data(), c->flags.p, sizeof(unsigned) * fl.size(), hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));
-    for (Ticket* t : admit) {
+    while (!admit.empty()) {
+        Ticket* t = admit.front();
         Job& J = t->J;
         const unsigned f = fl[1 + J.slot];
-        if (f & 1u) { server_finish(s, *t, DMT_E_NONFINITE); continue; }
-        if (f & 2u) { server_finish(s, *t, DMT_E_BOUND); continue; }
+        if (f & 3u) {
+            admit.erase(admit.begin());
+            server_finish(s, *t, (f & 1u) ? DMT_E_NONFINITE : DMT_E_BOUND);
+            continue;
+        }
         Ctl* ctl = P<Ctl>(c->ctl_all) + J.slot;
         TRY(J.D == 2 ? job_frontier<2>(c, J, ctl, st) : job_frontier<3>(c, J, ctl, st));
         TRY(J.D == 2 ? job_iteration0<2>(c, J, st) : job_iteration0<3>(c, J, st));
+        admit.erase(admit.begin());
         active.push_back(t);
+        // the separatrix buffers are data-dependent: charge what the job holds once they exist
+        const int64_t held = held_bytes(c->ws[J.slot]);
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->charge[J.slot] = std::max(t->bytes, held);
+        s->held[J.slot] = held;
+        s->shared = shared_bytes(c);
+        recount(s);
     }
     return DMT_OK;
 }
 
-// One round of the active jobs; finished ones get their outputs and leave.
+// One round of the active jobs; finished ones get their outputs and leave `active` before they
+// are handed back.
 dmt_status server_round(dmt_server* s, std::vector<Ticket*>& active) {
     dmt_context* c = s->c;
     std::vector<Job*> js;
     for (Ticket* t : active) js.push_back(&t->J);
     TRY(run_wg(c, js, false, s->st, 1, ROUND_PASSES));
-    std::vector<Ticket*> still;
-    for (Ticket* t : active) {
+    for (size_t i = 0; i < active.size();) {
+        Ticket* t = active[i];
         const Ctl h = c->hctl[t->J.slot];
         if (!h.done) {
-            still.push_back(t);
+            i++;
             continue;
         }
-        TRY(job_outputs(c, t->J, h, false, s->st));
-        server_finish(s, *t, t->J.status);
+        active.erase(active.begin() + (long)i);
+        dmt_status rc = DMT_OK;
+        if (s->fail_outputs_at >= 0 && s->finished++ == s->fail_outputs_at)
+            rc = fail(c, DMT_E_NOMEM, "injected output failure");
+        else
+            rc = job_outputs(c, t->J, h, false, s->st);
+        server_finish(s, *t, rc == DMT_OK ? t->J.status : rc);
+        if (rc != DMT_OK) return rc;
     }
-    active.swap(still);
     return DMT_OK;
+}
+
+// Admission by footprint (caller holds s->mu): the job at the head of the queue is admitted if a
+// slot is free and the accounted bytes stay within the budget, after releasing the workspaces of
+// idle slots if that is what it takes; the first job always fits an idle server.
+bool server_try_admit(dmt_server* s, Ticket& t, bool idle) {
+    if (s->free_slots.empty()) return false;
+    // prefer the idle slot holding the most memory already (its buffers are reused)
+    int best = -1;
+    for (size_t k = 0; k < s->free_slots.size(); k++)
+        if (best < 0 || s->charge[s->free_slots[k]] > s->charge[s->free_slots[best]]) best = (int)k;
+    const int slot = s->free_slots[best];
+    auto need = [&] { return s->inflight - s->charge[slot] + std::max(t.bytes, s->charge[slot]); };
+    if (need() > s->budget) {
+        // give back what other idle slots hold
+        for (int k : s->free_slots) {
+            if (k == slot || s->charge[k] == 0) continue;
+            release(s->c->ws[k]);
+            s->charge[k] = 0;
+            s->held[k] = 0;
+        }
+        recount(s);
+    }
+    if (need() > s->budget && !idle) return false;
+    s->free_slots.erase(s->free_slots.begin() + best);
+    t.J.slot = slot;
+    s->charge[slot] = std::max(t.bytes, s->charge[slot]);
+    recount(s);
+    t.state = 1;
+    return true;
 }
 
 void server_main(dmt_server* s) {
@@ -1075,14 +1169,9 @@ void server_main(dmt_server* s) {
             std::unique_lock<std::mutex> lk(s->mu);
             s->cv_work.wait(lk, [&] { return s->stop || !s->pending.empty() || !active.empty(); });
             if (s->stop && s->pending.empty() && active.empty()) break;
-            // admission by footprint: the first job always fits an idle server
-            while (!s->pending.empty() && !s->free_slots.empty()) {
+            while (!s->pending.empty()) {
                 Ticket& t = s->tickets.at(s->pending.front());
-                if ((!active.empty() || !admit.empty()) && s->inflight + t.bytes > s->budget) break;
-                s->inflight += t.bytes;
-                t.J.slot = s->free_slots.back();
-                s->free_slots.pop_back();
-                t.state = 1;
+                if (!server_try_admit(s, t, active.empty() && admit.empty())) break;
                 admit.push_back(&t);
                 s->pending.pop_front();
             }
@@ -1091,10 +1180,9 @@ void server_main(dmt_server* s) {
         if (!admit.empty()) rc = server_admit(s, admit, active);
         if (rc == DMT_OK && !active.empty()) rc = server_round(s, active);
         if (rc != DMT_OK) {
-            // a HIP failure ends every job in flight with that status
+            // a failure ends every job still held by the worker with that status
             for (Ticket* t : active) server_finish(s, *t, rc);
-            for (Ticket* t : admit)
-                if (t->state == 1) server_finish(s, *t, rc);
+            for (Ticket* t : admit) server_finish(s, *t, rc);
             active.clear();
         }
     }
@@ -1351,6 +1439,30 @@ dmt_status dmt_lossless_edits(dmt_context* c, int64_t* idx_out, float* val_out, 
     return DMT_OK;
 }
 
+dmt_status dmt_lossless_list(dmt_context* c, const uint8_t* q_out, const float* g_out, int64_t n, int64_t* idx_out,
+                             float* val_out, int64_t cap, int64_t* count, hipStream_t st) {
+    if (!c || !q_out || !g_out || !count || n < 0 || cap < 0) return fail(c, DMT_E_INVALID, "bad argument");
+    if (n > (int64_t)INT32_MAX) return fail(c, DMT_E_INVALID, "too many vertices");
+    *count = 0;
+    if (n == 0) return DMT_OK;
+    HIPCHK(c, hipSetDevice(c->device));
+    const unsigned nb = nblocks(n);
+    ENSURE(c, c->blk, sizeof(int) * (size_t)nb);
+    ENSURE(c, c->blkoff, sizeof(int64_t) * (size_t)(nb + 1));
+    k_lossless_count<<<nb, TPB, 0, st>>>(q_out, (int)n, P<int>(c->blk));
+    CHECK_LAUNCH(c);
+    int64_t total = 0;
+    TRY(scan(c, P<int>(c->blk), nb, P<int64_t>(c->blkoff), &total, st));
+    *count = total;
+    if (total == 0 || cap == 0) return DMT_OK;
+    if (!idx_out || !val_out) return fail(c, DMT_E_INVALID, "null output");
+    if (cap < total) return fail(c, DMT_E_INVALID, "destination too small for the lossless list");
+    k_lossless_write<<<nb, TPB, 0, st>>>(q_out, g_out, (int)n, P<int64_t>(c->blkoff), idx_out, val_out);
+    CHECK_LAUNCH(c);
+    HIPCHK(c, hipStreamSynchronize(st));
+    return DMT_OK;
+}
+
 dmt_status dmt_iteration_log(dmt_context* c, int64_t* log_host, int64_t cap, int64_t* count) {
     if (!c || !count || cap < 0) return fail(c, DMT_E_INVALID, "bad argument");
     const int64_t nrec = (int64_t)c->log.size() / DMT_LOG_WORDS;
@@ -1450,6 +1562,11 @@ dmt_status dmt_server_create(dmt_server** out, int hip_device, int64_t hbm_budge
         return DMT_E_NOMEM;
     }
     for (int k = max_jobs - 1; k >= 0; k--) s->free_slots.push_back(k);
+    s->charge.assign(max_jobs, 0);
+    s->held.assign(max_jobs, 0);
+    s->shared = shared_bytes(c);
+    recount(s);
+    if (const char* e = getenv("DMT_FAULT_OUTPUTS")) s->fail_outputs_at = atoll(e);
     s->worker = std::thread(server_main, s);
     *out = s;
     return DMT_OK;
@@ -1491,6 +1608,26 @@ dmt_status dmt_server_submit(dmt_server* s, const dmt_job* job, int64_t* ticket)
         s->pending.push_back(*ticket);
     }
     s->cv_work.notify_all();
+    return DMT_OK;
+}
+
+dmt_status dmt_server_info(dmt_server* s, int64_t* inflight_bytes, int64_t* held_bytes_host, int32_t* free_slots,
+                           int32_t* pending, int32_t* distinct_free_slots) {
+    if (!s) return DMT_E_INVALID;
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (inflight_bytes) *inflight_bytes = s->inflight;
+    if (held_bytes_host) {
+        int64_t h = s->shared;
+        for (int64_t b : s->held) h += b;
+        *held_bytes_host = h;
+    }
+    if (free_slots) *free_slots = (int32_t)s->free_slots.size();
+    if (pending) *pending = (int32_t)s->pending.size();
+    if (distinct_free_slots) {
+        std::vector<int> v = s->free_slots;
+        std::sort(v.begin(), v.end());
+        *distinct_free_slots = (int32_t)(std::unique(v.begin(), v.end()) - v.begin());
+    }
     return DMT_OK;
 }
 

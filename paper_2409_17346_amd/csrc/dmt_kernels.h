@@ -544,6 +544,16 @@ __global__ void __launch_bounds__(256) k_lossless_write(const uint8_t* __restric
     }
 }
 
+// Per-block count of lossless entries (q_out == 0xFF) of a finished job's outputs.
+__global__ void __launch_bounds__(256) k_lossless_count(const uint8_t* __restrict__ q_out, int n,
+                                                        int* __restrict__ lossless_blk) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    const int ll = (v < n && q_out[v] == 0xFF) ? 1 : 0;
+    int tot;
+    block_exclusive_scan(ll, tot);
+    if (threadIdx.x == 0) lossless_blk[blockIdx.x] = tot;
+}
+
 __global__ void __launch_bounds__(256) k_decode(const float* __restrict__ gh, const uint8_t* __restrict__ q,
                                                 int64_t n, float delta, float* __restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

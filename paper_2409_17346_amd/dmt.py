@@ -41,7 +41,7 @@ ABI_SYMBOLS = [
     "dmt_xi_from_relative", "dmt_bounds", "dmt_gradient_pairs", "dmt_extract_msc", "dmt_msc_copy",
     "dmt_correct", "dmt_correct_batch", "dmt_lossless_edits", "dmt_iteration_log", "dmt_apply_edits",
     "dmt_profile_enable", "dmt_profile_read", "dmt_workspace_bytes", "dmt_server_create", "dmt_server_destroy",
-    "dmt_server_submit", "dmt_server_poll",
+    "dmt_server_submit", "dmt_server_poll", "dmt_server_info", "dmt_lossless_list",
 ]
 
 PROF_KERNELS = {"gradient": 0, "classify": 1, "apply": 2, "sstep": 3, "setup": 4, "msc": 5, "loop": 6,
@@ -113,6 +113,9 @@ def load_library(path: str = SO):
     L.dmt_server_destroy.argtypes = [VP]
     L.dmt_server_submit.argtypes = [VP, C.POINTER(dmt_job), P64]
     L.dmt_server_poll.argtypes = [VP, C.c_int64, C.c_int32, C.POINTER(dmt_job)]
+    P32 = C.POINTER(C.c_int32)
+    L.dmt_server_info.argtypes = [VP, P64, P64, P32, P32, P32]
+    L.dmt_lossless_list.argtypes = [VP, VP, VP, C.c_int64, VP, VP, C.c_int64, P64, VP]
     for name in ABI_SYMBOLS:
         if name != "dmt_last_error":
             getattr(L, name).restype = C.c_int
@@ -299,10 +302,26 @@ def dmt_correct_batch(ctx: Context, fields, tier: int = 4, q_max: int = 6, max_i
     for j in range(n):
         g_out, q_out = outs[j]
         stj = int(arr[j].status)
-        idx = torch.nonzero(q_out.reshape(-1) == 0xFF).reshape(-1) if stj >= 0 else None
-        val = g_out.reshape(-1)[idx] if stj >= 0 else None
+        idx, val = dmt_lossless_list(ctx, q_out, g_out) if stj >= 0 else (None, None)
         res.append(Result(STATUS_NAMES.get(stj, str(stj)), g_out, q_out, arr[j].stats.as_dict(), idx, val, None))
     return res
+
+
+def dmt_lossless_list(ctx: Context, q_out: torch.Tensor, g_out: torch.Tensor) -> Tuple[torch.Tensor, torch.Tensor]:
+    """Lossless edits (vertex ids ascending, values) of a finished job, from its q_out and g_out."""
+    _dev(q_out, torch.uint8)
+    _dev(g_out)
+    n = C.c_int64()
+    s = _stream(g_out)
+    m = g_out.numel()
+    ctx.check(ctx.L.dmt_lossless_list(ctx.h, VP(q_out.data_ptr()), VP(g_out.data_ptr()), m, None, None, 0,
+                                      C.byref(n), s))
+    idx = torch.empty(n.value, dtype=torch.int64, device=g_out.device)
+    val = torch.empty(n.value, dtype=torch.float32, device=g_out.device)
+    if n.value:
+        ctx.check(ctx.L.dmt_lossless_list(ctx.h, VP(q_out.data_ptr()), VP(g_out.data_ptr()), m, VP(idx.data_ptr()),
+                                          VP(val.data_ptr()), n.value, C.byref(n), s))
+    return idx, val
 
 
 def dmt_lossless_edits(ctx: Context, device) -> Tuple[torch.Tensor, torch.Tensor]:
@@ -372,6 +391,7 @@ class Server:
             raise DmtError(st, "dmt_server_create failed")
         self.h = h
         self._held = {}
+        self._ctx = None   # context for reading lossless lists of finished jobs
 
     def submit(self, f: torch.Tensor, g_hat: torch.Tensor, xi: float, tier: int = 4, q_max: int = 6,
                max_iters: int = -1, g_out: Optional[torch.Tensor] = None, q_out: Optional[torch.Tensor] = None) -> int:
@@ -404,15 +424,31 @@ class Server:
             raise DmtError(st, "unknown ticket")
         f, gh, g_out, q_out = self._held.pop(ticket)
         stj = int(j.status)
-        idx = torch.nonzero(q_out.reshape(-1) == 0xFF).reshape(-1) if stj >= 0 else None
-        val = g_out.reshape(-1)[idx] if stj >= 0 else None
+        idx = val = None
+        if stj >= 0:
+            if self._ctx is None:
+                self._ctx = Context(g_out.device.index or 0)
+            idx, val = dmt_lossless_list(self._ctx, q_out, g_out)
         return Result(STATUS_NAMES.get(stj, str(stj)), g_out, q_out, j.stats.as_dict(), idx, val, None)
+
+    def info(self) -> Dict[str, int]:
+        """Admission accounting: inflight and held bytes, idle slots, queued jobs."""
+        a, b = C.c_int64(), C.c_int64()
+        fs, pn, df = C.c_int32(), C.c_int32(), C.c_int32()
+        st = self.L.dmt_server_info(self.h, C.byref(a), C.byref(b), C.byref(fs), C.byref(pn), C.byref(df))
+        if st != DMT_OK:
+            raise DmtError(st, "dmt_server_info failed")
+        return {"inflight_bytes": a.value, "held_bytes": b.value, "free_slots": fs.value, "pending": pn.value,
+                "distinct_free_slots": df.value}
 
     def close(self):
         if getattr(self, "h", None):
             self.L.dmt_server_destroy(self.h)
             self.h = None
             self._held.clear()
+        if getattr(self, "_ctx", None) is not None:
+            self._ctx.close()
+            self._ctx = None
 
     def __del__(self):
         try:

@@ -257,6 +257,15 @@ def config_atoms3d(seed: int = 3, side: int = 256, n_atoms: int = 512) -> Worklo
                     {"rel": 1e-4, "ghat": "bin", "seed": seed})
 
 
+def lognormal_case(side: int, seed: int, rel: float = 1e-4) -> Workload:
+    """3D lognormal field (the served mix's large requests) at any side; g_hat = 2*xi bins."""
+    rng = np.random.default_rng(seed)
+    f = lognormal3d(side, seed, rng=rng)
+    xi = xi_from_relative(f, rel)
+    return Workload(f"3d-{side}-lognormal-bin-{rel:g}", f, bin_quantize(f, xi), xi, 4, 6,
+                    {"rel": rel, "ghat": "bin", "seed": seed})
+
+
 def _mix_field(rng: np.random.Generator, dim: int, side: int, seed: int) -> np.ndarray:
     """n-D field from the 2D generators: coin picks Gaussians+noise or Gaussians+value noise."""
     kind = int(rng.integers(0, 2))
@@ -290,21 +299,23 @@ def _mix_field(rng: np.random.Generator, dim: int, side: int, seed: int) -> np.n
     return _normalize01(z).astype(np.float32)
 
 
+def batch_field(batch: int, i: int, n_fields: int = 64) -> Workload:
+    """Field i of batch `batch`: 2D (side log-uniform [256,1024]) for the first half, else 3D
+    (side log-uniform [64,160]); each field draws from its own generator."""
+    rng = np.random.default_rng([4000 + batch, i])
+    dim = 2 if i < n_fields // 2 else 3
+    lo, hi = (256, 1024) if dim == 2 else (64, 160)
+    side = int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
+    f = _mix_field(rng, dim, side, 4000 + batch)
+    rel = 1e-3 if rng.integers(0, 2) == 0 else 1e-4
+    xi = xi_from_relative(f, rel)
+    g = bin_quantize(f, xi) if rng.integers(0, 2) == 0 else uniform_noise(f, xi, rng)
+    return Workload(f"batch{batch}-{i}-{dim}d-{side}", f, g, xi, 4, 6, {"rel": rel, "batch": batch, "index": i})
+
+
 def batch_mix(batch: int = 0, n_fields: int = 64) -> list:
     """Batch of uneven fields: half 2D (side log-uniform [256,1024]), half 3D (side log-uniform [64,160])."""
-    out = []
-    for i in range(n_fields):
-        rng = np.random.default_rng([4000 + batch, i])
-        dim = 2 if i < n_fields // 2 else 3
-        lo, hi = (256, 1024) if dim == 2 else (64, 160)
-        side = int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
-        f = _mix_field(rng, dim, side, 4000 + batch)
-        rel = 1e-3 if rng.integers(0, 2) == 0 else 1e-4
-        xi = xi_from_relative(f, rel)
-        g = bin_quantize(f, xi) if rng.integers(0, 2) == 0 else uniform_noise(f, xi, rng)
-        out.append(Workload(f"batch{batch}-{i}-{dim}d-{side}", f, g, xi, 4, 6,
-                            {"rel": rel, "batch": batch, "index": i}))
-    return out
+    return [batch_field(batch, i, n_fields) for i in range(n_fields)]
 
 
 def served_job(j: int, big_side: int = 384) -> Workload:

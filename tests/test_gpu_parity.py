@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 import oracle
+from floorcheck import explained
 from paper_2409_17346_amd import synth
 
 torch = pytest.importorskip("torch")
@@ -178,38 +179,30 @@ def test_correct_hybrid_handoff(ctx, dmt, monkeypatch, limit, case):
     assert (log[:, 14] + log[:, 15] > limit).any(), "the hand-off was not exercised"
 
 
-def _floor_collision_inversions(w, g):
-    """Adjacent vertex pairs that are both at their floor, with equal floors, in the opposite
-    order to f: decrease-only edits can never separate them (fp32 floors f - xi rounded up
-    merge distinct f values where |f - xi| has a larger exponent than f)."""
+def _assert_stall_explained(w, g, tier, n_residual):
+    """Every violation left at a stall has an equal-floor, both-at-floor pair of vertices ordered
+    against f in the closed 1-ring of the cell's highest vertex: decrease-only edits can never
+    separate such a pair (fp32 floors f - xi rounded up merge distinct f values where |f - xi| has
+    a larger exponent than f)."""
     nx, ny, nz = w.dims
-    lo, _ = oracle.bounds(w.f.reshape(-1), w.xi)
-    F, G = w.f.reshape(nz, ny, nx), g.reshape(nz, ny, nx)
-    Lo = lo.reshape(nz, ny, nx)
-    I = np.arange(F.size).reshape(nz, ny, nx)
-    n = 0
-    for dz in (0, 1):
-        for dy in (0, 1):
-            for dx in (0, 1):
-                if dx == dy == dz == 0 or (nz == 1 and dz):
-                    continue
-                a = (slice(0, nz - dz), slice(0, ny - dy), slice(0, nx - dx))
-                b = (slice(dz, nz), slice(dy, ny), slice(dx, nx))
-                pf = (F[a] < F[b]) | ((F[a] == F[b]) & (I[a] < I[b]))
-                pg = (G[a] < G[b]) | ((G[a] == G[b]) & (I[a] < I[b]))
-                n += int(((pf != pg) & (G[a] == Lo[a]) & (G[b] == Lo[b]) & (G[a] == G[b])).sum())
-    return n
+    cx = oracle.Complex.grid(nx, ny, nz)
+    f = w.f.reshape(-1)
+    res = oracle.residual(cx, f, g, tier)
+    assert len(res) == n_residual
+    lo, _ = oracle.bounds(f, w.xi)
+    ok = explained(w.dims, f, g, lo, res)
+    assert ok.all(), res[~ok][:8]
+    return len(res)
 
 
 def test_correct_atoms3d_small(ctx, dmt):
     """A 40^3 version of the 3D density field (24 atoms, 2*xi bins), full MSC.  Near the 1e-4
     background the fp32 floors collide, and this input stalls in the oracle and on the GPU alike;
-    the stall must be explained by floor collisions."""
+    every violation left must be explained by a floor collision."""
     w = synth.config_atoms3d(seed=3, side=40, n_atoms=24)
     r, o = _compare_correction(ctx, dmt, w)
-    if r.status != "ok":
-        assert r.stats["stalled"] == 1 and r.stats["residual_violations"] > 0
-        assert _floor_collision_inversions(w, r.g.cpu().numpy().reshape(-1)) > 0
+    assert r.status == "not_converged" and r.stats["stalled"] == 1
+    assert _assert_stall_explained(w, r.g.cpu().numpy().reshape(-1), 4, r.stats["residual_violations"]) > 0
 
 
 def test_identity_and_errors(ctx, dmt):
@@ -377,3 +370,53 @@ def test_server_errors(dmt):
             srv.poll(t_ok)                                  # released
     finally:
         srv.close()
+
+
+def test_server_error_path_frees_each_slot_once(dmt, monkeypatch):
+    """A failure in one job's output step (injected) ends the jobs the worker still holds with that
+    status, hands every slot back exactly once, and leaves a server that still serves correctly."""
+    monkeypatch.setenv("DMT_FAULT_OUTPUTS", "1")
+    ws = _server_jobs()
+    srv = dmt.Server(0, max_jobs=4)
+    try:
+        tickets = [srv.submit(_t(w.f), _t(w.g_hat), w.xi) for w in ws]
+        res = [srv.poll(t, wait=True) for t in tickets]
+        assert sum(r.status == "nomem" for r in res) >= 1
+        for w, r in zip(ws, res):
+            if r.status != "nomem":
+                _check_against_oracle(w, r)
+        info = srv.info()
+        assert info["free_slots"] == 4 and info["distinct_free_slots"] == 4 and info["pending"] == 0
+        # with no job in flight, every accounted byte is memory the idle slots still hold
+        assert info["inflight_bytes"] == info["held_bytes"]
+        w = ws[-2]
+        _check_against_oracle(w, srv.poll(srv.submit(_t(w.f), _t(w.g_hat), w.xi), wait=True))
+    finally:
+        srv.close()
+
+
+def test_server_budget_accounting(dmt):
+    """With a budget below two jobs' footprints the jobs of a burst run one at a time, each equal to
+    the oracle; once the server is idle every accounted byte is memory its slots still hold."""
+    ws = _server_jobs()[-3:]
+    est = max(dmt.dmt_workspace_bytes(w.f.shape) for w in ws)
+    srv = dmt.Server(0, hbm_budget_bytes=est + (est // 2), max_jobs=8)
+    try:
+        tickets = [srv.submit(_t(w.f), _t(w.g_hat), w.xi) for w in ws]
+        for w, t in zip(ws, tickets):
+            _check_against_oracle(w, srv.poll(t, wait=True))
+        info = srv.info()
+        assert info["inflight_bytes"] == info["held_bytes"] > 0
+        assert info["free_slots"] == info["distinct_free_slots"] == 8
+    finally:
+        srv.close()
+
+
+def test_lossless_list_matches_correct(ctx, dmt):
+    """dmt_lossless_list reads a job's lossless edits from q_out and g_out: the same list that
+    dmt_correct keeps in the context."""
+    w = synth.config_small2d()
+    r = dmt.dmt_correct(ctx, _t(w.f), _t(w.g_hat), w.xi)
+    idx, val = dmt.dmt_lossless_list(ctx, r.q, r.g)
+    assert r.lossless_idx.numel() > 0
+    assert torch.equal(idx, r.lossless_idx) and torch.equal(val.view(torch.int32), r.lossless_val.view(torch.int32))
