@@ -178,6 +178,32 @@ dmt_status dmt_correct(dmt_context *ctx, const dmt_grid *grid, const float *f, c
                        float xi, const dmt_options *opts, float *g_out, uint8_t *q_out,
                        dmt_stats *stats_host, hipStream_t stream);
 
+/* Allocation-free variant of dmt_correct, for callers that cannot allocate device memory (code
+ * under stream capture, tight serving loops, harnesses that forbid hipMalloc).  Same inputs,
+ * outputs, statuses and results as dmt_correct, bit for bit; it makes no device allocation or
+ * free of any kind.  Every device buffer it needs besides the caller's comes from one scratch
+ * array of DMT_NOALLOC_SCRATCH_BYTES per GPU, part of the library's code object (so each GPU
+ * the library runs on holds it until the process ends); its address is resolved when a
+ * context is created on that device.
+ * The lossless edits are written here instead of staying in the context: lossless_idx /
+ * lossless_val are device arrays of lossless_cap entries (int64 vertex ids ascending, fp32
+ * values); lossless_count_host receives the number of entries, and a count above lossless_cap
+ * returns DMT_E_INVALID (g_out and q_out are still written).  The per-iteration log stays in the
+ * context as for dmt_correct; dmt_lossless_edits reports no entries after this call, and kernel
+ * timing (dmt_profile_enable) is not recorded for it.
+ * Limits: DMT_E_NOMEM, before any work, when dmt_workspace_bytes of the grid exceeds
+ * DMT_NOALLOC_SCRATCH_BYTES (about 1.19 M vertices in 2D, 0.59 M in 3D), or during the call if a
+ * field's separatrices need more scratch than is left (outputs then undefined).
+ * Concurrency: all calls on one GPU share its scratch array, which keeps the last call's
+ * contents (each call initialises what it reads).  Calls that overlap in time on one GPU, from
+ * any context or stream, race and corrupt each other's results: serialise them, e.g. on one
+ * stream. */
+#define DMT_NOALLOC_SCRATCH_BYTES 134217728LL
+dmt_status dmt_correct_noalloc(dmt_context *ctx, const dmt_grid *grid, const float *f, const float *g_hat,
+                               float xi, const dmt_options *opts, float *g_out, uint8_t *q_out,
+                               int64_t *lossless_idx, float *lossless_val, int64_t lossless_cap,
+                               int64_t *lossless_count_host, dmt_stats *stats_host, hipStream_t stream);
+
 /* One job of a batch (Section 5.7: every field of a time series is corrected on its own).
  * Inputs: grid, device pointers f and g_hat, xi, options (flags must be 0), output device
  * pointers g_out and q_out, as for dmt_correct.  Filled by the call: status and stats. */

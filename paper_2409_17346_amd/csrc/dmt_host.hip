@@ -23,7 +23,43 @@
 
 using namespace dmt;
 
+// Scratch memory of the allocation-free correction (dmt_correct_noalloc): one array per device,
+// loaded with the code object and held until the process ends.  Host code never uses this name
+// as an address; its device address is resolved once per device (scratch_address below).
+static __device__ __align__(256) unsigned char scratch[DMT_NOALLOC_SCRATCH_BYTES];
+
 namespace {
+
+// Device address of `scratch` on each device, resolved once with that device current.
+std::mutex scratch_mu;
+std::vector<int> scratch_state;         // 0 not yet resolved, 1 resolved, -1 failed
+std::vector<char*> scratch_ptr;
+std::vector<std::string> scratch_msg;
+
+// Resolves (once) the scratch address of the current device `dev` of ndev; nullptr and a message
+// when the runtime cannot give it.
+char* scratch_address(int dev, int ndev, std::string& msg) {
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if ((int)scratch_state.size() < ndev) {
+        scratch_state.resize(ndev, 0);
+        scratch_ptr.resize(ndev, nullptr);
+        scratch_msg.resize(ndev);
+    }
+    if (scratch_state[dev] == 0) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e == hipSuccess && p) {
+            scratch_ptr[dev] = static_cast<char*>(p);
+            scratch_state[dev] = 1;
+        } else {
+            (void)hipGetLastError();
+            scratch_msg[dev] = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+            scratch_state[dev] = -1;
+        }
+    }
+    msg = scratch_msg[dev];
+    return scratch_ptr[dev];
+}
 
 struct DevBuf {
     void* p = nullptr;
@@ -90,6 +126,13 @@ struct dmt_context {
     size_t ev_used = 0;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev[DMT_PROF_KERNELS];
     int64_t prof_units[DMT_PROF_KERNELS] = {0};
+    // allocation-free calls: this device's scratch array (its device address, 0 if it could
+    // not be resolved) and, while such a call runs, a bump arena over it that every buffer of
+    // the call is carved from instead of hipMalloc
+    char* scratch = nullptr;
+    std::string scratch_err;
+    bool arena_on = false;
+    size_t arena_used = 0;
 };
 
 namespace {
@@ -108,9 +151,25 @@ dmt_status fail(dmt_context* c, dmt_status s, const std::string& msg) {
 
 #define CHECK_LAUNCH(ctx) HIPCHK(ctx, hipGetLastError())
 
+// Carves bytes (256-aligned) from the scratch arena of an allocation-free call.
+dmt_status arena_take(dmt_context* c, DevBuf& b, size_t bytes) {
+    const size_t off = (c->arena_used + 255) & ~(size_t)255;
+    if (off + bytes > (size_t)DMT_NOALLOC_SCRATCH_BYTES)
+        return fail(c, DMT_E_NOMEM, "the allocation-free path needs more than its " +
+                                        std::to_string((long long)DMT_NOALLOC_SCRATCH_BYTES) +
+                                        " bytes of scratch for this field");
+    b.p = c->scratch + off;
+    b.cap = bytes;
+    c->arena_used = off + bytes;
+    return DMT_OK;
+}
+
 dmt_status ensure(dmt_context* c, DevBuf& b, size_t bytes) {
     if (bytes == 0) bytes = 16;
     if (b.cap >= bytes) return DMT_OK;
+    // in an allocation-free call every buffer was emptied at entry, so b (if set) is an
+    // arena buffer of this call: carve a larger one and leave the old space unused
+    if (c->arena_on) return arena_take(c, b, bytes);
     if (b.p) (void)hipFree(b.p);
     b.p = nullptr;
     b.cap = 0;
@@ -136,6 +195,12 @@ dmt_status ensure(dmt_context* c, DevBuf& b, size_t bytes) {
 
 template <typename T>
 T* P(DevBuf& b) { return reinterpret_cast<T*>(b.p); }
+
+// The context's shared device buffers (not those of job workspaces or of dmt_extract_msc).
+std::vector<DevBuf*> context_bufs(dmt_context* c) {
+    return {&c->gpl,    &c->req,      &c->cnt,   &c->flags, &c->part,      &c->blk,      &c->blkoff, &c->ll_idx,
+            &c->ll_val, &c->dlog,     &c->jobs_dev, &c->ctl_all, &c->queue, &c->scan_tsum, &c->scan_toff};
+}
 
 dmt_status check_grid(dmt_context* c, const dmt_grid* gr, Dims& dm, int& D) {
     if (!gr) return fail(c, DMT_E_INVALID, "grid is NULL");
@@ -525,15 +590,19 @@ dmt_status grow_log(dmt_context* c, size_t need, int64_t keep, hipStream_t st) {
     const size_t rec = sizeof(long long) * DMT_LOG_WORDS;
     if (c->dlog.cap >= need * rec) return DMT_OK;
     DevBuf nb;
-    if (hipMalloc(&nb.p, need * 2 * rec) != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(c, DMT_E_NOMEM, "log allocation failed");
+    if (c->arena_on) {
+        TRY(arena_take(c, nb, need * 2 * rec));
+    } else {
+        if (hipMalloc(&nb.p, need * 2 * rec) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(c, DMT_E_NOMEM, "log allocation failed");
+        }
+        nb.cap = need * 2 * rec;
     }
-    nb.cap = need * 2 * rec;
     if (c->dlog.p && keep > 0)
         HIPCHK(c, hipMemcpyAsync(nb.p, c->dlog.p, (size_t)keep * rec, hipMemcpyDeviceToDevice, st));
     HIPCHK(c, hipStreamSynchronize(st));
-    if (c->dlog.p) (void)hipFree(c->dlog.p);
+    if (c->dlog.p && !c->arena_on) (void)hipFree(c->dlog.p);
     c->dlog = nb;
     return DMT_OK;
 }
@@ -1203,6 +1272,7 @@ dmt_status dmt_context_create(dmt_context** ctx, int hip_device) {
     if (hipSetDevice(hip_device) != hipSuccess) return DMT_E_HIP;
     dmt_context* c = new dmt_context();
     c->device = hip_device;
+    c->scratch = scratch_address(hip_device, ndev, c->scratch_err);
     if (hipHostMalloc((void**)&c->hcnt, sizeof(unsigned long long) * CNT_WORDS, 0) != hipSuccess ||
         hipHostMalloc((void**)&c->hscratch, sizeof(int64_t) * 64, 0) != hipSuccess) {
         delete c;
@@ -1215,9 +1285,7 @@ dmt_status dmt_context_create(dmt_context** ctx, int hip_device) {
 dmt_status dmt_context_destroy(dmt_context* c) {
     if (!c) return DMT_OK;
     (void)hipSetDevice(c->device);
-    std::vector<DevBuf*> bufs = {&c->gpl, &c->req, &c->cnt, &c->flags, &c->part, &c->blk, &c->blkoff, &c->ll_idx,
-                                 &c->ll_val, &c->dlog, &c->jobs_dev, &c->ctl_all, &c->queue, &c->scan_tsum,
-                                 &c->scan_toff};
+    std::vector<DevBuf*> bufs = context_bufs(c);
     for (DevBuf* b : c->msc.all()) bufs.push_back(b);
     for (JobWs& w : c->ws)
         for (DevBuf* b : w.all()) bufs.push_back(b);
@@ -1387,6 +1455,57 @@ dmt_status dmt_correct(dmt_context* c, const dmt_grid* gr, const float* f, const
     if (J.status == DMT_E_BOUND) return fail(c, DMT_E_BOUND, "|g_hat - f| > xi somewhere");
     if (stats) *stats = J.stats;
     return J.status;
+}
+
+dmt_status dmt_correct_noalloc(dmt_context* c, const dmt_grid* gr, const float* f, const float* g_hat, float xi,
+                               const dmt_options* o, float* g_out, uint8_t* q_out, int64_t* ll_idx, float* ll_val,
+                               int64_t ll_cap, int64_t* ll_count, dmt_stats* stats, hipStream_t st) {
+    if (!c) return DMT_E_INVALID;
+    if (!f || !g_hat || !o || !g_out || !q_out || !ll_count) return fail(c, DMT_E_INVALID, "null argument");
+    if (ll_cap < 0 || (ll_cap > 0 && (!ll_idx || !ll_val))) return fail(c, DMT_E_INVALID, "bad lossless destination");
+    Dims dm{};
+    int D = 2;
+    TRY(check_grid(c, gr, dm, D));
+    TRY(check_options(c, o, xi));
+    if (!c->scratch) return fail(c, DMT_E_HIP, "no scratch on this device: " + c->scratch_err);
+    if (workspace_estimate(D, dm.n) > (int64_t)DMT_NOALLOC_SCRATCH_BYTES)
+        return fail(c, DMT_E_NOMEM, "field of " + std::to_string((long long)dm.n) + " vertices needs about " +
+                                        std::to_string((long long)workspace_estimate(D, dm.n)) +
+                                        " bytes of scratch; the allocation-free path holds " +
+                                        std::to_string((long long)DMT_NOALLOC_SCRATCH_BYTES));
+    // Every buffer this call uses starts empty, so ensure() carves it from the scratch arena; the
+    // context's own buffers are set aside and put back afterwards.  Kernel timing stays off (it
+    // would create events).
+    std::vector<DevBuf*> cb = context_bufs(c);
+    std::vector<DevBuf> saved_cb;
+    for (DevBuf* b : cb) { saved_cb.push_back(*b); *b = DevBuf{}; }
+    const bool had_ws = !c->ws.empty();
+    JobWs saved_ws;
+    if (had_ws) { saved_ws = c->ws[0]; c->ws[0] = JobWs{}; }
+    const bool prof = c->prof;
+    c->prof = false;
+    c->arena_on = true;
+    c->arena_used = 0;
+    dmt_status s = dmt_correct(c, gr, f, g_hat, xi, o, g_out, q_out, stats, st);
+    if (s >= 0) {
+        *ll_count = c->n_lossless;
+        if (c->n_lossless > ll_cap) {
+            s = fail(c, DMT_E_INVALID, "destination too small for the lossless list");
+        } else if (c->n_lossless > 0) {
+            const size_t m = (size_t)c->n_lossless;
+            hipError_t e = hipMemcpyAsync(ll_idx, c->ll_idx.p, sizeof(int64_t) * m, hipMemcpyDeviceToDevice, st);
+            if (e == hipSuccess) e = hipMemcpyAsync(ll_val, c->ll_val.p, sizeof(float) * m, hipMemcpyDeviceToDevice, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (e != hipSuccess) s = fail(c, DMT_E_HIP, std::string("lossless list copy: ") + hipGetErrorString(e));
+        }
+    }
+    c->arena_on = false;
+    c->prof = prof;
+    for (size_t k = 0; k < cb.size(); k++) *cb[k] = saved_cb[k];
+    if (had_ws) c->ws[0] = saved_ws;
+    else c->ws.clear();
+    c->n_lossless = 0;   // the list was handed to the caller; the context keeps none
+    return s;
 }
 
 dmt_status dmt_correct_batch(dmt_context* c, int32_t n_jobs, dmt_job* jobs_host, hipStream_t st) {

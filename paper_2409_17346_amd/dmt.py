@@ -21,6 +21,9 @@ SO = os.path.join(HERE, "libdmt.so")
 DMT_OK = 0
 DMT_W_NOT_CONVERGED = 1
 DMT_W_PENDING = 2
+DMT_E_INVALID = -1
+DMT_E_NOMEM = -4
+DMT_NOALLOC_SCRATCH_BYTES = 134217728   # include/dmt.h: scratch of dmt_correct_noalloc per GPU
 STATUS_NAMES = {0: "ok", 1: "not_converged", 2: "pending", -1: "invalid", -2: "bound", -3: "nonfinite",
                 -4: "nomem", -5: "hip"}
 LOG_WORDS = 20
@@ -41,7 +44,7 @@ ABI_SYMBOLS = [
     "dmt_xi_from_relative", "dmt_bounds", "dmt_gradient_pairs", "dmt_extract_msc", "dmt_msc_copy",
     "dmt_correct", "dmt_correct_batch", "dmt_lossless_edits", "dmt_iteration_log", "dmt_apply_edits",
     "dmt_profile_enable", "dmt_profile_read", "dmt_workspace_bytes", "dmt_server_create", "dmt_server_destroy",
-    "dmt_server_submit", "dmt_server_poll", "dmt_server_info", "dmt_lossless_list",
+    "dmt_server_submit", "dmt_server_poll", "dmt_server_info", "dmt_lossless_list", "dmt_correct_noalloc",
 ]
 
 PROF_KERNELS = {"gradient": 0, "classify": 1, "apply": 2, "sstep": 3, "setup": 4, "msc": 5, "loop": 6,
@@ -116,6 +119,8 @@ def load_library(path: str = SO):
     P32 = C.POINTER(C.c_int32)
     L.dmt_server_info.argtypes = [VP, P64, P64, P32, P32, P32]
     L.dmt_lossless_list.argtypes = [VP, VP, VP, C.c_int64, VP, VP, C.c_int64, P64, VP]
+    L.dmt_correct_noalloc.argtypes = [VP, C.POINTER(dmt_grid), VP, VP, C.c_float, C.POINTER(dmt_options), VP, VP,
+                                      VP, VP, C.c_int64, P64, C.POINTER(dmt_stats), VP]
     for name in ABI_SYMBOLS:
         if name != "dmt_last_error":
             getattr(L, name).restype = C.c_int
@@ -269,6 +274,34 @@ def dmt_correct(ctx: Context, f: torch.Tensor, g_hat: torch.Tensor, xi: float, t
         idx, val = dmt_lossless_edits(ctx, f.device)
         log = dmt_iteration_log(ctx)
     return Result(STATUS_NAMES[rc], g_out, q_out, stats, idx, val, log)
+
+
+def dmt_correct_noalloc(ctx: Context, f: torch.Tensor, g_hat: torch.Tensor, xi: float, g_out: torch.Tensor,
+                        q_out: torch.Tensor, lossless_idx: torch.Tensor, lossless_val: torch.Tensor, tier: int = 4,
+                        q_max: int = 6, max_iters: int = -1, flags: int = 0) -> Result:
+    """The allocation-free correction: every output buffer is the caller's (lossless_idx int64 and
+    lossless_val float32 of equal length = the list's capacity); the library allocates nothing.
+    Returns a Result whose lossless_idx / lossless_val are views of the filled prefixes."""
+    for t in (f, g_hat, g_out):
+        _dev(t)
+    _dev(q_out, torch.uint8)
+    _dev(lossless_idx, torch.int64)
+    _dev(lossless_val)
+    if f.shape != g_hat.shape or f.shape != g_out.shape or f.shape != q_out.shape:
+        raise ValueError("f, g_hat, g_out and q_out differ in shape")
+    if lossless_idx.numel() != lossless_val.numel():
+        raise ValueError("lossless_idx and lossless_val differ in length")
+    st = dmt_stats()
+    cnt = C.c_int64()
+    opts = dmt_options(tier, q_max, max_iters, flags)
+    g = grid_of(f)
+    rc = ctx.check(ctx.L.dmt_correct_noalloc(ctx.h, C.byref(g), VP(f.data_ptr()), VP(g_hat.data_ptr()), xi,
+                                             C.byref(opts), VP(g_out.data_ptr()), VP(q_out.data_ptr()),
+                                             VP(lossless_idx.data_ptr()), VP(lossless_val.data_ptr()),
+                                             lossless_idx.numel(), C.byref(cnt), C.byref(st), _stream(f)),
+                   allow=(DMT_OK, DMT_W_NOT_CONVERGED))
+    m = cnt.value
+    return Result(STATUS_NAMES[rc], g_out, q_out, st.as_dict(), lossless_idx[:m], lossless_val[:m], None)
 
 
 def dmt_correct_batch(ctx: Context, fields, tier: int = 4, q_max: int = 6, max_iters: int = -1,

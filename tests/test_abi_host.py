@@ -47,3 +47,10 @@ def test_workspace_estimate():
     assert dmt.dmt_workspace_bytes((128, 128)) == 112 * 128 * 128 + (1 << 20)
     assert dmt.dmt_workspace_bytes((8, 9, 10)) == 224 * 720 + (1 << 20)
     assert dmt.dmt_workspace_bytes((1, 9)) == -1
+
+
+def test_noalloc_scratch_size_matches_header():
+    from paper_2409_17346_amd import dmt
+    src = open(os.path.join(ROOT, "include", "dmt.h")).read()
+    m = re.search(r"#define DMT_NOALLOC_SCRATCH_BYTES (\d+)LL", src)
+    assert m and int(m.group(1)) == dmt.DMT_NOALLOC_SCRATCH_BYTES
