@@ -89,39 +89,62 @@ def traffic_from_profiles(kernel_file: str):
         return None
 
 
-def cpu_baseline(w, crop: int):
-    """The oracle (single thread, as written) on a crop x crop corner of the same workload."""
-    import numpy as np
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, iterations: int, sample_iters: int):
+    """The oracle (single thread, as written) on the same full input, timed over a bounded number
+    of iterations and scaled to the whole correction.  The oracle recomputes everything densely in
+    every iteration, so its cost is a fixed part (building the complex, f's gradient and
+    separatrices, the first detection: the run with max_iters = 0) plus a per-iteration part
+    (from a run with max_iters = sample_iters); the estimate is fixed + per_iteration * iterations,
+    with iterations the full correction's count (equal on both sides by the parity tests)."""
     import oracle
-    if w.f.ndim == 2:
-        f = np.ascontiguousarray(w.f[:crop, :crop])
-        g = np.ascontiguousarray(w.g_hat[:crop, :crop])
-        cx = oracle.Complex.grid(f.shape[1], f.shape[0], 1)
-    else:
-        f = np.ascontiguousarray(w.f[:crop, :crop, :crop])
-        g = np.ascontiguousarray(w.g_hat[:crop, :crop, :crop])
-        cx = oracle.Complex.grid(f.shape[2], f.shape[1], f.shape[0])
+    nx, ny, nz = w.dims
+    cx = oracle.Complex.grid(nx, ny, nz)
+    f, g = w.f.reshape(-1), w.g_hat.reshape(-1)
     t0 = time.perf_counter()
-    r = oracle.correct(cx, f.reshape(-1), g.reshape(-1), w.xi, w.tier, w.q_max)
-    dt = time.perf_counter() - t0
-    return {"value": round(4.0 * f.size / dt / 1e6, 4), "unit": "MB/s", "cores": 1, "kind": "oracle",
-            "sample": f"{'x'.join(map(str, f.shape))} corner crop of the same field and g_hat, full correction "
-                      f"to convergence ({r['stats']['iterations']} iterations) in {dt:.1f} s on one host thread"}
+    oracle.correct(cx, f, g, w.xi, w.tier, w.q_max, max_iters=0)
+    fixed = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    r = oracle.correct(cx, f, g, w.xi, w.tier, w.q_max, max_iters=sample_iters)
+    part = time.perf_counter() - t0
+    done = r["stats"]["iterations"]
+    per_it = max(part - fixed, 0.0) / max(done, 1)
+    est = fixed + per_it * iterations
+    return {"value": round(4.0 * w.f.size / est / 1e6, 4), "unit": "MB/s", "cores": 1, "kind": "oracle",
+            "cpu": cpu_model(),
+            "sample": f"full {'x'.join(map(str, w.f.shape))} input: setup and first detection {fixed:.1f} s, then "
+                      f"{done} iterations in {part - fixed:.1f} s on one host thread; scaled to the correction's "
+                      f"{iterations} iterations = {est:.0f} s",
+            "seconds_estimated": round(est, 1)}
 
 
 def bench_batch(args):
     """The batched form: a step is one dmt_correct_batch call over 64 uneven fields (32 2D with
     side log-uniform in [256, 1024], 32 3D with side log-uniform in [64, 160], xi from
-    {1e-3, 1e-4} * range, g_hat binned or noisy)."""
+    {1e-3, 1e-4} * range, g_hat binned or noisy), with launch shapes from the autotuner.  The same
+    fields are also corrected one after another by 64 plain dmt_correct calls on one stream."""
     import numpy as np
     import torch
-    from paper_2409_17346_amd import dmt, synth
+    from paper_2409_17346_amd import autotune, dmt, synth
     ws = synth.batch_mix(0, 64)
     n_total = sum(w.f.size for w in ws)
     print(f"[bench] batch of {len(ws)} fields, {n_total} vertices", file=sys.stderr, flush=True)
     ctx = dmt.Context(0)
     fields = [(torch.from_numpy(w.f).cuda(), torch.from_numpy(w.g_hat).cuda(), w.xi) for w in ws]
     outs = [(torch.empty_like(f), torch.empty(f.shape, dtype=torch.uint8, device="cuda")) for f, _, _ in fields]
+    tuning, table = None, []
+    if not args.no_tune:
+        tuning, table = autotune.tune_batch(ctx, fields, outs, log=lambda m: print(m, file=sys.stderr, flush=True))
+        print(f"[bench] tuned: {tuning}", file=sys.stderr, flush=True)
     for i in range(args.warmup):
         res = dmt.dmt_correct_batch(ctx, fields, outputs=outs)
         print(f"[bench] warmup {i}: " + str({s: sum(r.status == s for r in res) for s in set(r.status for r in res)}),
@@ -131,11 +154,23 @@ def bench_batch(args):
     t0 = time.perf_counter()
     for i in range(args.steps):
         ts = time.perf_counter()
-        res = dmt.dmt_correct_batch(ctx, fields, outputs=outs)
+        res = dmt.dmt_correct_batch(ctx, fields, outputs=outs, lossless=False)
         lat.append(time.perf_counter() - ts)
         print(f"[bench] step {i}: {lat[-1] * 1e3:.1f} ms", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    # the plain path on the same fields: 64 dmt_correct calls, one after another, one stream
+    seq_out = [(torch.empty_like(f), torch.empty(f.shape, dtype=torch.uint8, device="cuda")) for f, _, _ in fields]
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    for (f, gh, xi), (go, qo) in zip(fields, seq_out):
+        dmt.dmt_correct(ctx, f, gh, xi, 4, 6, want_edits=False, g_out=go, q_out=qo)
+    torch.cuda.synchronize()
+    seq_s = time.perf_counter() - ts
+    same = all(torch.equal(a[0].view(torch.int32), b[0].view(torch.int32)) and torch.equal(a[1], b[1])
+               for a, b in zip(outs, seq_out))
+    print(f"[bench] 64 sequential calls: {seq_s * 1e3:.1f} ms, outputs identical: {same}", file=sys.stderr,
+          flush=True)
     dmt.dmt_profile_enable(ctx, True)
     res = dmt.dmt_correct_batch(ctx, fields, outputs=outs)
     prof = dmt.dmt_profile_read(ctx)
@@ -155,8 +190,11 @@ def bench_batch(args):
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "batch64-mixed-2d256-1024-3d64-160", "fields": len(ws), "vertices": n_total,
                    "tier": 4, "q_max": 6, "status": status, "iterations_max": max(iters),
-                   "iterations_median": int(np.median(iters))},
+                   "iterations_median": int(np.median(iters)), "tuning": tuning,
+                   "tuning_candidates_timed": len(table)},
         "latency_ms": {"p50": pct(50), "p99": pct(99)},
+        "sequential": {"ms": round(seq_s * 1e3, 3), "value": round(4.0 * n_total / seq_s / 1e6, 3), "unit": "MB/s",
+                       "outputs_identical": same, "speedup_of_batch": round(seq_s / (elapsed / args.steps), 3)},
         "kernel_ms": {k: round(v["ms"], 3) for k, v in prof.items()},
     }
     print(json.dumps(line), flush=True)
@@ -231,8 +269,12 @@ def main():
     ap.add_argument("--workload", default="large2d", choices=["large2d", "small2d", "atoms3d", "batch64", "served"])
     ap.add_argument("--requests", type=int, default=200, help="served: requests in the stream")
     ap.add_argument("--qps", type=float, default=4.0, help="served: Poisson arrival rate (requests/s)")
-    ap.add_argument("--cpu-crop", type=int, default=512)
+    ap.add_argument("--cpu-sample-iters", type=int, default=40,
+                    help="iterations of the oracle timed on the full input for the CPU baseline")
+    ap.add_argument("--no-extra-configs", action="store_true",
+                    help="skip the 128x128 and 256^3 configurations after the headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="batch64: keep the default launch shapes")
     ap.add_argument("--flags", type=int, default=0, help="dmt_options.flags (1 dense loop, 2 one launch per phase)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first copy a buffer of this many MiB once (untimed): the reference kernel that scales "
@@ -259,46 +301,84 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     w = workload(args.workload)
-    print(f"[bench] workload {w.name} shape {w.f.shape} xi {w.xi:.6g}", file=sys.stderr, flush=True)
     ctx = dmt.Context(0)
+    line = bench_single(ctx, dmt, torch, w, args.steps, args.warmup, args.flags, full=True)
+    if not args.no_extra_configs and args.workload == "large2d" and args.flags == 0:
+        # the other single-field configurations, timed the same way (kernel roofline of the headline only)
+        extra = {}
+        for name, steps in (("small2d", 20), ("atoms3d", 2)):
+            wx = workload(name)
+            lx = bench_single(ctx, dmt, torch, wx, steps, 1, 0, full=False)
+            extra[wx.name] = {"value": lx["value"], "unit": "MB/s", "ms_per_step": lx["ms_per_step"],
+                              "steps": steps, "latency_ms": lx["latency_ms"], **lx["config"]}
+        line["other_configs"] = extra
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(w, line["config"]["iterations"], args.cpu_sample_iters)
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+def bench_single(ctx, dmt, torch, w, steps: int, warmup: int, flags: int, full: bool) -> dict:
+    """Times `steps` corrections of one field (after `warmup` untimed ones); with full, also the
+    kernel rooflines from one more profiled correction."""
+    print(f"[bench] workload {w.name} shape {w.f.shape} xi {w.xi:.6g}", file=sys.stderr, flush=True)
     f = torch.from_numpy(w.f).cuda()
     gh = torch.from_numpy(w.g_hat).cuda()
     g_out = torch.empty_like(f)
     q_out = torch.empty(f.shape, dtype=torch.uint8, device="cuda")
     n = f.numel()
 
-    for i in range(args.warmup):
+    for i in range(warmup):
         r = dmt.dmt_correct(ctx, f, gh, w.xi, w.tier, w.q_max, want_edits=False, g_out=g_out, q_out=q_out,
-                            flags=args.flags)
+                            flags=flags)
         print(f"[bench] warmup {i}: {r.status} {r.stats}", file=sys.stderr, flush=True)
 
     lat = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(args.steps):
+    for i in range(steps):
         ts = time.perf_counter()
         r = dmt.dmt_correct(ctx, f, gh, w.xi, w.tier, w.q_max, want_edits=False, g_out=g_out, q_out=q_out,
-                            flags=args.flags)
+                            flags=flags)
         lat.append(time.perf_counter() - ts)
         print(f"[bench] step {i}: {lat[-1] * 1e3:.1f} ms {r.status} iterations={r.stats['iterations']}",
               file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    # kernel timing: one more (untimed) step with HIP events around the library's launches, which
-    # also returns the per-iteration work counters
-    dmt.dmt_profile_enable(ctx, True)
-    rp = dmt.dmt_correct(ctx, f, gh, w.xi, w.tier, w.q_max, want_edits=True, g_out=g_out, q_out=q_out,
-                         flags=args.flags)
-    prof = dmt.dmt_profile_read(ctx)
-    dmt.dmt_profile_enable(ctx, False)
-
-    value = 4.0 * n * args.steps / elapsed / 1e6
+    value = 4.0 * n * steps / elapsed / 1e6
     lat_sorted = sorted(lat)
 
     def pct(p):
         k = min(len(lat_sorted) - 1, max(0, int(round(p / 100.0 * (len(lat_sorted) - 1)))))
         return round(lat_sorted[k] * 1e3, 3)
 
+    line = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "MB/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": round(elapsed / steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "dims": list(w.dims), "tier": w.tier, "q_max": w.q_max,
+                   "rel_error_bound": w.meta.get("rel"), "status": r.status, "iterations": r.stats["iterations"],
+                   "c_iterations": r.stats["c_iterations"], "s_iterations": r.stats["s_iterations"],
+                   "residual_violations": r.stats["residual_violations"]},
+        "latency_ms": {"p50": pct(50), "p99": pct(99)},
+    }
+    if not full:
+        return line
+    # kernel timing: one more (untimed) step with HIP events around the library's launches, which
+    # also returns the per-iteration work counters
+    dmt.dmt_profile_enable(ctx, True)
+    rp = dmt.dmt_correct(ctx, f, gh, w.xi, w.tier, w.q_max, want_edits=True, g_out=g_out, q_out=q_out, flags=flags)
+    prof = dmt.dmt_profile_read(ctx)
+    dmt.dmt_profile_enable(ctx, False)
     ndim = w.ndim
 
     def roof(fam, alg_total):
@@ -311,33 +391,11 @@ def main():
                 "launches": p["launches"], "avg_launch_us": round(avg_ms * 1e3, 3), "alg_bytes_per_launch": int(alg)}
 
     # the dominant kernel is the correction loop (resident workgroup loop plus its grid hand-offs)
-    loop_roof = roof("loop", loop_bytes(rp.log.numpy(), ndim))
-    grad_roof = roof("gradient", bytes_per_unit("gradient", ndim) * prof["gradient"]["units"])
-    line = {
-        "metric": METRIC,
-        "value": round(value, 3),
-        "unit": "MB/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(elapsed / args.steps * 1e3, 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": w.name, "dims": list(w.dims), "tier": w.tier, "q_max": w.q_max,
-                   "rel_error_bound": w.meta.get("rel"), "iterations": r.stats["iterations"],
-                   "c_iterations": r.stats["c_iterations"], "s_iterations": r.stats["s_iterations"]},
-        "latency_ms": {"p50": pct(50), "p99": pct(99)},
-        "roofline": loop_roof,
-        "roofline_dense_gradient": grad_roof,
-        "kernel_ms": {k: round(v["ms"], 3) for k, v in prof.items()},
-    }
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(w, args.cpu_crop)
-    print(json.dumps(line), flush=True)
-    ctx.close()
+    line["roofline"] = roof("loop", loop_bytes(rp.log.numpy(), ndim))
+    line["roofline_dense_gradient"] = roof("gradient", bytes_per_unit("gradient", ndim) * prof["gradient"]["units"])
+    line["roofline_dense_classify"] = roof("classify", bytes_per_unit("classify", ndim) * prof["classify"]["units"])
+    line["kernel_ms"] = {k: round(v["ms"], 3) for k, v in prof.items()}
+    return line
 
 
 if __name__ == "__main__":

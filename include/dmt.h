@@ -204,6 +204,29 @@ dmt_status dmt_correct_noalloc(dmt_context *ctx, const dmt_grid *grid, const flo
                                int64_t *lossless_idx, float *lossless_val, int64_t lossless_cap,
                                int64_t *lossless_count_host, dmt_stats *stats_host, hipStream_t stream);
 
+/* Launch shapes of the correction loop (Section 4.8: the GPU form of the C/S loops).  They change
+ * speed only: every setting gives bit-identical results.  Index 0 is for 2D jobs, 1 for 3D jobs,
+ * except grid_iterations: 0 for dmt_correct, 1 for batches and the server.
+ *   loop_threads     threads of the workgroup that runs one job's loop: 512 or 1024 for 2D,
+ *                    256 or 512 for 3D (fewer threads leave more registers per lane);
+ *   handoff_anchors  an iteration with more affected plus listed anchors than this (or a
+ *                    troublemaker pass over more candidate branches) leaves the workgroup and runs
+ *                    as full-grid launches, one per phase; 0 never hands off;
+ *   grid_iterations  iterations run as full-grid launches per hand-off (1..4096).
+ * Defaults: {1024, 512}, {8192, 8192}, {4, 64}.  The autotuner of the Python package picks them
+ * per workload by timing candidates. */
+typedef struct {
+    int32_t loop_threads[2];
+    int32_t handoff_anchors[2];
+    int32_t grid_iterations[2];
+} dmt_tuning;
+
+/* Sets the launch shapes of later calls on ctx (NULL restores the defaults).  DMT_E_INVALID for
+ * values outside the ranges above (the context keeps its setting). */
+dmt_status dmt_set_tuning(dmt_context *ctx, const dmt_tuning *tuning);
+/* Reads the launch shapes of ctx into tuning_host. */
+dmt_status dmt_get_tuning(const dmt_context *ctx, dmt_tuning *tuning_host);
+
 /* One job of a batch (Section 5.7: every field of a time series is corrected on its own).
  * Inputs: grid, device pointers f and g_hat, xi, options (flags must be 0), output device
  * pointers g_out and q_out, as for dmt_correct.  Filled by the call: status and stats. */

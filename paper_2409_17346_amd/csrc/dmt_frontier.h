@@ -948,17 +948,13 @@ __device__ __forceinline__ void run_job_wg(const FrontierView& B, int max_passes
     __syncthreads();
 }
 
-// Workgroup size of the resident loop: the 3D passes need twice the registers of the 2D ones.
-template <int D>
-struct WgThreads {
-    static constexpr int value = D == 2 ? 1024 : 512;
-};
-
-// Workgroups take jobs (all of dimension D) from a queue (an atomic counter starting at 0)
-// until none is left.
-template <int D>
-__global__ void __launch_bounds__(WgThreads<D>::value) k_fr_loop_wg(const FrontierBufs* __restrict__ jobs,
-                                                                    int n_jobs, int* queue, int max_passes, int big) {
+// Workgroups of NT threads take jobs (all of dimension D) from a queue (an atomic counter
+// starting at 0) until none is left.  NT is a tuning choice (512 or 1024 threads in 2D, 256 or
+// 512 in 3D): fewer threads give each lane more registers (the 3D passes need about twice those
+// of the 2D ones), more threads cover larger frontiers per step; results do not depend on it.
+template <int D, int NT>
+__global__ void __launch_bounds__(NT) k_fr_loop_wg(const FrontierBufs* __restrict__ jobs, int n_jobs, int* queue,
+                                                   int max_passes, int big) {
     __shared__ int job_sh;
     for (;;) {
         if (threadIdx.x == 0) job_sh = atomicAdd(queue, 1);

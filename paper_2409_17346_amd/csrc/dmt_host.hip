@@ -102,6 +102,20 @@ struct JobWs {
 
 }  // namespace
 
+namespace {
+// The launch shapes the library uses unless dmt_set_tuning says otherwise.
+dmt_tuning default_tuning() {
+    dmt_tuning t;
+    t.loop_threads[0] = 1024;
+    t.loop_threads[1] = 512;
+    t.handoff_anchors[0] = 8192;
+    t.handoff_anchors[1] = 8192;
+    t.grid_iterations[0] = 4;
+    t.grid_iterations[1] = 64;
+    return t;
+}
+}  // namespace
+
 struct dmt_context {
     int device = 0;
     std::string err;
@@ -126,6 +140,7 @@ struct dmt_context {
     size_t ev_used = 0;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev[DMT_PROF_KERNELS];
     int64_t prof_units[DMT_PROF_KERNELS] = {0};
+    dmt_tuning tune = default_tuning();
     // allocation-free calls: this device's scratch array (its device address, 0 if it could
     // not be resolved) and, while such a call runs, a bump arena over it that every buffer of
     // the call is carved from instead of hipMalloc
@@ -641,10 +656,13 @@ dmt_status run_wg(dmt_context* c, std::vector<Job*>& jobs, bool with_log, hipStr
     const int nj = (int)jobs.size();
     int ncu = 0, occ2 = 0, occ3 = 0;
     HIPCHK(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device));
-    HIPCHK(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ2, reinterpret_cast<const void*>(k_fr_loop_wg<2>),
-                                                           WgThreads<2>::value, 0));
-    HIPCHK(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ3, reinterpret_cast<const void*>(k_fr_loop_wg<3>),
-                                                           WgThreads<3>::value, 0));
+    const int nt2 = c->tune.loop_threads[0], nt3 = c->tune.loop_threads[1];
+    const void* loop2 = nt2 == 512 ? reinterpret_cast<const void*>(k_fr_loop_wg<2, 512>)
+                                   : reinterpret_cast<const void*>(k_fr_loop_wg<2, 1024>);
+    const void* loop3 = nt3 == 256 ? reinterpret_cast<const void*>(k_fr_loop_wg<3, 256>)
+                                   : reinterpret_cast<const void*>(k_fr_loop_wg<3, 512>);
+    HIPCHK(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ2, loop2, nt2, 0));
+    HIPCHK(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ3, loop3, nt3, 0));
     if (occ2 < 1 || occ3 < 1) return fail(c, DMT_E_HIP, "the loop kernel does not fit a compute unit");
     // jobs ordered 2D first, then 3D; hb[k] belongs to jobs[order[k]] and to control block
     // order[k] (control blocks follow the order of jobs)
@@ -674,14 +692,12 @@ dmt_status run_wg(dmt_context* c, std::vector<Job*>& jobs, bool with_log, hipStr
     // launches (a workgroup takes about 1 us per 100 such anchors, the grid far less); the loop
     // kernel ends once every job has finished or paused, then the host runs a few iterations of
     // each paused job on the whole grid and launches the loop again
-    int big = 8192;
-    if (const char* e = getenv("DMT_WG_MAX_ANCHORS")) big = atoi(e);
+    const int big2 = c->tune.handoff_anchors[0], big3 = c->tune.handoff_anchors[1];
     std::vector<int> pos(nj);
     for (int k = 0; k < nj; k++) pos[order[k]] = k;
     // a paused job of a batch waits for every other workgroup to finish or pause before the
     // host can run its grid iterations, so batches hand over more iterations at a time
-    int grid_batch = nj == 1 ? 4 : 64;
-    if (const char* e = getenv("DMT_GRID_BATCH")) grid_batch = atoi(e) > 0 ? atoi(e) : grid_batch;
+    const int grid_batch = c->tune.grid_iterations[nj == 1 ? 0 : 1];
     int64_t progress = -1;
     for (int launch = 0; max_launches < 0 || launch < max_launches; launch++) {
         HIPCHK(c, hipMemsetAsync(c->queue.p, 0, sizeof(int) * 2, st));
@@ -704,13 +720,20 @@ dmt_status run_wg(dmt_context* c, std::vector<Job*>& jobs, bool with_log, hipStr
             }
             if (n2) {
                 const int blocks = n2 < ncu * occ2 ? n2 : ncu * occ2;
-                k_fr_loop_wg<2><<<blocks, WgThreads<2>::value, 0, st>>>(jd, n2, P<int>(c->queue), max_passes, big);
+                if (nt2 == 512)
+                    k_fr_loop_wg<2, 512><<<blocks, 512, 0, st>>>(jd, n2, P<int>(c->queue), max_passes, big2);
+                else
+                    k_fr_loop_wg<2, 1024><<<blocks, 1024, 0, st>>>(jd, n2, P<int>(c->queue), max_passes, big2);
                 CHECK_LAUNCH(c);
             }
             if (nj > n2) {
                 const int blocks = nj - n2 < ncu * occ3 ? nj - n2 : ncu * occ3;
-                k_fr_loop_wg<3><<<blocks, WgThreads<3>::value, 0, s3>>>(jd + n2, nj - n2, P<int>(c->queue) + 1,
-                                                                         max_passes, big);
+                if (nt3 == 256)
+                    k_fr_loop_wg<3, 256><<<blocks, 256, 0, s3>>>(jd + n2, nj - n2, P<int>(c->queue) + 1, max_passes,
+                                                                 big3);
+                else
+                    k_fr_loop_wg<3, 512><<<blocks, 512, 0, s3>>>(jd + n2, nj - n2, P<int>(c->queue) + 1, max_passes,
+                                                                 big3);
                 CHECK_LAUNCH(c);
             }
             if (mixed) {
@@ -1506,6 +1529,30 @@ dmt_status dmt_correct_noalloc(dmt_context* c, const dmt_grid* gr, const float* 
     else c->ws.clear();
     c->n_lossless = 0;   // the list was handed to the caller; the context keeps none
     return s;
+}
+
+dmt_status dmt_set_tuning(dmt_context* c, const dmt_tuning* t) {
+    if (!c) return DMT_E_INVALID;
+    if (!t) {
+        c->tune = default_tuning();
+        return DMT_OK;
+    }
+    if ((t->loop_threads[0] != 512 && t->loop_threads[0] != 1024) ||
+        (t->loop_threads[1] != 256 && t->loop_threads[1] != 512))
+        return fail(c, DMT_E_INVALID, "loop_threads must be 512 or 1024 (2D) and 256 or 512 (3D)");
+    for (int k = 0; k < 2; k++) {
+        if (t->handoff_anchors[k] < 0) return fail(c, DMT_E_INVALID, "handoff_anchors must be >= 0");
+        if (t->grid_iterations[k] < 1 || t->grid_iterations[k] > 4096)
+            return fail(c, DMT_E_INVALID, "grid_iterations must be in 1..4096");
+    }
+    c->tune = *t;
+    return DMT_OK;
+}
+
+dmt_status dmt_get_tuning(const dmt_context* c, dmt_tuning* t) {
+    if (!c || !t) return DMT_E_INVALID;
+    *t = c->tune;
+    return DMT_OK;
 }
 
 dmt_status dmt_correct_batch(dmt_context* c, int32_t n_jobs, dmt_job* jobs_host, hipStream_t st) {

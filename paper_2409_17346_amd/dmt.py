@@ -45,6 +45,7 @@ ABI_SYMBOLS = [
     "dmt_correct", "dmt_correct_batch", "dmt_lossless_edits", "dmt_iteration_log", "dmt_apply_edits",
     "dmt_profile_enable", "dmt_profile_read", "dmt_workspace_bytes", "dmt_server_create", "dmt_server_destroy",
     "dmt_server_submit", "dmt_server_poll", "dmt_server_info", "dmt_lossless_list", "dmt_correct_noalloc",
+    "dmt_set_tuning", "dmt_get_tuning",
 ]
 
 PROF_KERNELS = {"gradient": 0, "classify": 1, "apply": 2, "sstep": 3, "setup": 4, "msc": 5, "loop": 6,
@@ -72,6 +73,14 @@ class dmt_stats(C.Structure):
 
     def as_dict(self) -> Dict[str, int]:
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+class dmt_tuning(C.Structure):
+    _fields_ = [("loop_threads", C.c_int32 * 2), ("handoff_anchors", C.c_int32 * 2),
+                ("grid_iterations", C.c_int32 * 2)]
+
+    def as_dict(self) -> Dict[str, list]:
+        return {k: list(getattr(self, k)) for k, _ in self._fields_}
 
 
 class dmt_job(C.Structure):
@@ -119,6 +128,8 @@ def load_library(path: str = SO):
     P32 = C.POINTER(C.c_int32)
     L.dmt_server_info.argtypes = [VP, P64, P64, P32, P32, P32]
     L.dmt_lossless_list.argtypes = [VP, VP, VP, C.c_int64, VP, VP, C.c_int64, P64, VP]
+    L.dmt_set_tuning.argtypes = [VP, C.POINTER(dmt_tuning)]
+    L.dmt_get_tuning.argtypes = [VP, C.POINTER(dmt_tuning)]
     L.dmt_correct_noalloc.argtypes = [VP, C.POINTER(dmt_grid), VP, VP, C.c_float, C.POINTER(dmt_options), VP, VP,
                                       VP, VP, C.c_int64, P64, C.POINTER(dmt_stats), VP]
     for name in ABI_SYMBOLS:
@@ -304,10 +315,29 @@ def dmt_correct_noalloc(ctx: Context, f: torch.Tensor, g_hat: torch.Tensor, xi: 
     return Result(STATUS_NAMES[rc], g_out, q_out, st.as_dict(), lossless_idx[:m], lossless_val[:m], None)
 
 
+def dmt_set_tuning(ctx: Context, tuning: Optional[Dict[str, list]] = None) -> None:
+    """Sets the loop's launch shapes ({"loop_threads": [2D, 3D], "handoff_anchors": [2D, 3D],
+    "grid_iterations": [single, batch]}); None restores the defaults."""
+    if tuning is None:
+        ctx.check(ctx.L.dmt_set_tuning(ctx.h, None))
+        return
+    t = dmt_tuning()
+    for k, v in tuning.items():
+        arr = getattr(t, k)
+        arr[0], arr[1] = int(v[0]), int(v[1])
+    ctx.check(ctx.L.dmt_set_tuning(ctx.h, C.byref(t)))
+
+
+def dmt_get_tuning(ctx: Context) -> Dict[str, list]:
+    t = dmt_tuning()
+    ctx.check(ctx.L.dmt_get_tuning(ctx.h, C.byref(t)))
+    return t.as_dict()
+
+
 def dmt_correct_batch(ctx: Context, fields, tier: int = 4, q_max: int = 6, max_iters: int = -1,
-                      outputs=None):
+                      outputs=None, lossless: bool = True):
     """Corrects a list of (f, g_hat, xi) jobs together.  Returns a list of Result (lossless edits
-    derived from q == 0xFF; no per-iteration log)."""
+    read by the library from q == 0xFF unless lossless is False; no per-iteration log)."""
     n = len(fields)
     arr = (dmt_job * n)()
     outs = []
@@ -335,7 +365,7 @@ def dmt_correct_batch(ctx: Context, fields, tier: int = 4, q_max: int = 6, max_i
     for j in range(n):
         g_out, q_out = outs[j]
         stj = int(arr[j].status)
-        idx, val = dmt_lossless_list(ctx, q_out, g_out) if stj >= 0 else (None, None)
+        idx, val = dmt_lossless_list(ctx, q_out, g_out) if stj >= 0 and lossless else (None, None)
         res.append(Result(STATUS_NAMES.get(stj, str(stj)), g_out, q_out, arr[j].stats.as_dict(), idx, val, None))
     return res
 

@@ -162,7 +162,7 @@ def test_correct_large2d_crop(ctx, dmt, flags):
 
 @pytest.mark.parametrize("limit", [1, 8, 64])
 @pytest.mark.parametrize("case", ["small2d", "tiny3d", "crop2d"])
-def test_correct_hybrid_handoff(ctx, dmt, monkeypatch, limit, case):
+def test_correct_hybrid_handoff(ctx, dmt, limit, case):
     """Iterations with more affected + listed anchors than the limit leave the resident loop for
     full-grid launches and come back: results and log stay those of the oracle."""
     if case == "small2d":
@@ -173,8 +173,12 @@ def test_correct_hybrid_handoff(ctx, dmt, monkeypatch, limit, case):
         w = synth.config_large2d()
         w.f = np.ascontiguousarray(w.f[:96, :128])
         w.g_hat = np.ascontiguousarray(w.g_hat[:96, :128])
-    monkeypatch.setenv("DMT_WG_MAX_ANCHORS", str(limit))
-    r, o = _compare_correction(ctx, dmt, w)
+    dmt.dmt_set_tuning(ctx, {"loop_threads": [1024, 512], "handoff_anchors": [limit, limit],
+                             "grid_iterations": [4, 64]})
+    try:
+        r, o = _compare_correction(ctx, dmt, w)
+    finally:
+        dmt.dmt_set_tuning(ctx, None)
     log = r.log.numpy()
     assert (log[:, 14] + log[:, 15] > limit).any(), "the hand-off was not exercised"
 
@@ -261,14 +265,18 @@ def test_correct_batch_matches_oracle_and_single(ctx, dmt, tier):
         assert torch.equal(s.g.view(torch.int32), r.g.view(torch.int32)) and torch.equal(s.q, r.q)
 
 
-def test_correct_batch_concurrent_handoff(ctx, dmt, monkeypatch):
+@pytest.mark.parametrize("threads", [(1024, 512), (512, 256)], ids=["wg1024-512", "wg512-256"])
+def test_correct_batch_concurrent_handoff(ctx, dmt, threads):
     """With a low hand-off limit several jobs of a batch pause together and run their full-grid
-    iterations side by side on separate streams: every job still equals the oracle."""
-    monkeypatch.setenv("DMT_WG_MAX_ANCHORS", "16")
-    monkeypatch.setenv("DMT_GRID_BATCH", "2")
+    iterations side by side on separate streams: every job still equals the oracle, with either
+    choice of loop workgroup sizes."""
     ws = _batch_jobs()
     fields = [(_t(w.f), _t(w.g_hat), w.xi) for w in ws]
-    res = dmt.dmt_correct_batch(ctx, fields, tier=4, q_max=6)
+    dmt.dmt_set_tuning(ctx, {"loop_threads": list(threads), "handoff_anchors": [16, 16], "grid_iterations": [4, 2]})
+    try:
+        res = dmt.dmt_correct_batch(ctx, fields, tier=4, q_max=6)
+    finally:
+        dmt.dmt_set_tuning(ctx, None)
     for w, r in zip(ws, res):
         nx, ny, nz = w.dims
         o = oracle.correct(oracle.Complex.grid(nx, ny, nz), w.f.reshape(-1), w.g_hat.reshape(-1), w.xi, 4, 6)
@@ -278,6 +286,45 @@ def test_correct_batch_concurrent_handoff(ctx, dmt, monkeypatch):
                 assert r.stats[k] == v, (w.name, k)
         assert np.array_equal(r.g.cpu().numpy().reshape(-1).view(np.uint32), o["g"].view(np.uint32)), w.name
         assert np.array_equal(r.q.cpu().numpy().reshape(-1), o["q"]), w.name
+
+
+@pytest.mark.parametrize("threads", [(512, 256), (1024, 512)], ids=["wg512-256", "wg1024-512"])
+@pytest.mark.parametrize("limit", [0, 8192])
+def test_tuning_keeps_results(ctx, dmt, threads, limit):
+    """Every launch shape gives the oracle's results (2D crop with S-iterations, small 3D field)."""
+    dmt.dmt_set_tuning(ctx, {"loop_threads": list(threads), "handoff_anchors": [limit, limit],
+                             "grid_iterations": [16, 64]})
+    try:
+        assert dmt.dmt_get_tuning(ctx)["loop_threads"] == list(threads)
+        w = synth.config_large2d()
+        w.f = np.ascontiguousarray(w.f[:96, :128])
+        w.g_hat = np.ascontiguousarray(w.g_hat[:96, :128])
+        _compare_correction(ctx, dmt, w)
+        _compare_correction(ctx, dmt, synth.tiny_cases(13, (12, 10, 9), rel=0.05, kind="smooth", ghat="noise"))
+    finally:
+        dmt.dmt_set_tuning(ctx, None)
+
+
+def test_tuning_rejects_bad_values(ctx, dmt):
+    before = dmt.dmt_get_tuning(ctx)
+    for bad in ({"loop_threads": [256, 512]}, {"loop_threads": [1024, 1024]}, {"handoff_anchors": [-1, 0]},
+                {"grid_iterations": [0, 4]}, {"grid_iterations": [4, 5000]}):
+        t = {k: list(v) for k, v in before.items()}
+        t.update(bad)
+        with pytest.raises(dmt.DmtError):
+            dmt.dmt_set_tuning(ctx, t)
+        assert dmt.dmt_get_tuning(ctx) == before
+
+
+def test_autotuner_picks_a_setting(ctx, dmt):
+    from paper_2409_17346_amd import autotune
+    w = synth.config_small2d()
+    best, table = autotune.tune_single(ctx, _t(w.f), _t(w.g_hat), w.xi, repeats=1)
+    try:
+        assert dmt.dmt_get_tuning(ctx) == best
+        assert len(table) > 4 and min(r["seconds"] for r in table) > 0
+    finally:
+        dmt.dmt_set_tuning(ctx, None)
 
 
 def test_correct_batch_isolates_bad_jobs(ctx, dmt):
