@@ -201,64 +201,122 @@ def bench_batch(args):
     ctx.close()
 
 
-def bench_served(args):
-    """The served form: a Poisson stream of correction requests into dmt_server.  Requests draw
-    their fields from a pool: 23 fields like the batch mix (2D side 256-1024, 3D side 64-160,
-    xi = 1e-4 * range) and one 384^3 lognormal 3D field used by the ~5% large requests.  Reports
-    MB/s of fields completed over the stream's wall time and p50/p99 request latency (arrival to
-    completion)."""
+def _arrival_stream(qps: float, n: int, seed: int):
     import numpy as np
-    import torch
-    from paper_2409_17346_amd import dmt, synth
-    rng = np.random.default_rng(6000)
-    big_ids = [j for j in range(args.requests) if np.random.default_rng(5000 + j).uniform() < 0.05]
-    small = [synth.served_job(j) for j in range(40) if np.random.default_rng(5000 + j).uniform() >= 0.05][:23]
-    big = synth.served_job(big_ids[0]) if big_ids else None
-    pool = [(torch.from_numpy(w.f).cuda(), torch.from_numpy(w.g_hat).cuda(), w.xi, w.f.size) for w in small]
-    bigt = (torch.from_numpy(big.f).cuda(), torch.from_numpy(big.g_hat).cuda(), big.xi, big.f.size) if big else None
-    reqs = [bigt if j in big_ids else pool[int(rng.integers(0, len(pool)))] for j in range(args.requests)]
-    arrivals = np.cumsum(rng.exponential(1.0 / args.qps, size=args.requests))
-    print(f"[bench] served: {args.requests} requests ({len(big_ids)} of 384^3) at {args.qps} req/s",
-          file=sys.stderr, flush=True)
+    return np.cumsum(np.random.default_rng(seed).exponential(1.0 / qps, size=n))
+
+
+def _run_served(dmt, torch, reqs, arrivals, log_every: int = 50):
+    """Continuous batching: requests enter dmt_server as they arrive.  Returns latencies (s),
+    statuses and the stream's wall time (first arrival to last completion)."""
     srv = dmt.Server(0, hbm_budget_bytes=96 << 30, max_jobs=64)
-    # warmup: one request of each pool field kind
-    for r in reqs[:args.warmup]:
-        srv.poll(srv.submit(r[0], r[1], r[2]), wait=True)
-    torch.cuda.synchronize()
+    outs = {}
     t0 = time.perf_counter()
-    nxt, live, lat, status, done_bytes = 0, {}, [], {}, 0.0
-    t_last = t0
+    nxt, live, lat, status, t_last = 0, {}, [None] * len(reqs), {}, t0
     while nxt < len(reqs) or live:
         now = time.perf_counter() - t0
         while nxt < len(reqs) and arrivals[nxt] <= now:
-            f, g, xi, n = reqs[nxt]
-            live[srv.submit(f, g, xi)] = (arrivals[nxt], n)
+            f, g, xi = reqs[nxt][:3]
+            live[srv.submit(f, g, xi)] = nxt
             nxt += 1
         for t in list(live):
-            res = srv.poll(t)
+            res = srv.poll(t, lossless=False)
             if res is not None:
-                a, n = live.pop(t)
+                j = live.pop(t)
                 t_last = time.perf_counter()
-                lat.append(t_last - t0 - a)
-                done_bytes += 4.0 * n
+                lat[j] = t_last - t0 - arrivals[j]
+                outs[j] = (res.g, res.q)
                 status[res.status] = status.get(res.status, 0) + 1
-                if len(lat) % 20 == 0:
-                    print(f"[bench] {len(lat)} done, latency p50 {np.percentile(lat, 50):.3f} s", file=sys.stderr,
-                          flush=True)
-        time.sleep(0.0005)
-    elapsed = t_last - t0
+                done = sum(x is not None for x in lat)
+                if done % log_every == 0:
+                    print(f"[bench] served: {done} done", file=sys.stderr, flush=True)
+        if not live and nxt < len(reqs):
+            time.sleep(max(0.0, min(0.002, arrivals[nxt] - (time.perf_counter() - t0))))
+        else:
+            time.sleep(0.0002)
     srv.close()
-    lat_ms = np.array(lat) * 1e3
+    return lat, status, t_last - t0, outs
+
+
+def _run_fifo(dmt, torch, ctx, reqs, arrivals, log_every: int = 50):
+    """The plain path under the same arrivals: one dmt_correct at a time, in arrival order."""
+    t0 = time.perf_counter()
+    lat, status, outs = [], {}, {}
+    for j, (f, g, xi, _) in enumerate(reqs):
+        wait = arrivals[j] - (time.perf_counter() - t0)
+        if wait > 0:
+            time.sleep(wait)
+        go, qo = torch.empty_like(f), torch.empty(f.shape, dtype=torch.uint8, device="cuda")
+        r = dmt.dmt_correct(ctx, f, g, xi, 4, 6, want_edits=False, g_out=go, q_out=qo)
+        lat.append(time.perf_counter() - t0 - arrivals[j])
+        outs[j] = (go, qo)
+        status[r.status] = status.get(r.status, 0) + 1
+        if (j + 1) % log_every == 0:
+            print(f"[bench] fifo: {j + 1} done", file=sys.stderr, flush=True)
+    return lat, status, time.perf_counter() - t0, outs
+
+
+def bench_served(args):
+    """The served form: a Poisson stream of correction requests (synth.served_job: 5% 384^3
+    lognormal fields, the rest like the batch mix, xi = 1e-4 * range).  The plain path's capacity
+    is measured first (every request through dmt_correct back to back); the stream then arrives at
+    0.5x and 0.8x that rate, once into dmt_server (continuous batching) and once through the plain
+    path one request at a time in arrival order (FIFO).  Reports MB/s of fields completed and
+    p50/p99 latency (arrival to completion) of each, and checks that every request's outputs are
+    the same in both."""
+    import numpy as np
+    import torch
+    from paper_2409_17346_amd import dmt, synth
+    n = args.requests
+    t0 = time.perf_counter()
+    reqs = []
+    for j in range(n):
+        w = synth.served_job(j)
+        reqs.append((torch.from_numpy(w.f).cuda(), torch.from_numpy(w.g_hat).cuda(), w.xi, w.f.size))
+        if (j + 1) % 50 == 0:
+            print(f"[bench] generated {j + 1} requests ({time.perf_counter() - t0:.0f} s)", file=sys.stderr, flush=True)
+    n_big = sum(1 for r in reqs if r[3] == 384 ** 3)
+    total_bytes = 4.0 * sum(r[3] for r in reqs)
+    ctx = dmt.Context(0)
+    # warm both paths on a few requests (kernels loaded, buffers grown)
+    for f, g, xi, _ in reqs[:max(1, args.warmup)]:
+        dmt.dmt_correct(ctx, f, g, xi, 4, 6, want_edits=False)
+    cap_lat, _, cap_s, _ = _run_fifo(dmt, torch, ctx, reqs, np.zeros(n))
+    capacity = n / cap_s
+    print(f"[bench] plain capacity {capacity:.2f} req/s ({cap_s:.1f} s for {n} requests)", file=sys.stderr,
+          flush=True)
+    runs = {}
+    for load in (0.5, 0.8):
+        qps = load * capacity
+        arr = _arrival_stream(qps, n, 6000)
+        s_lat, s_st, s_wall, s_out = _run_served(dmt, torch, reqs, arr)
+        f_lat, f_st, f_wall, f_out = _run_fifo(dmt, torch, ctx, reqs, arr)
+        same = all(torch.equal(s_out[j][0].view(torch.int32), f_out[j][0].view(torch.int32)) and
+                   torch.equal(s_out[j][1], f_out[j][1]) for j in range(n))
+
+        def summary(lat, st, wall):
+            ms = np.array(lat) * 1e3
+            return {"value": round(total_bytes / wall / 1e6, 3), "unit": "MB/s", "wall_s": round(wall, 3),
+                    "p50_ms": round(float(np.percentile(ms, 50)), 3), "p99_ms": round(float(np.percentile(ms, 99)), 3),
+                    "status": st}
+
+        runs[f"load{load}"] = {"qps": round(qps, 3), "served": summary(s_lat, s_st, s_wall),
+                               "fifo": summary(f_lat, f_st, f_wall), "outputs_identical": same}
+        print(f"[bench] load {load}: {json.dumps(runs[f'load{load}'])}", file=sys.stderr, flush=True)
+    head = runs["load0.8"]["served"]
     line = {
-        "metric": METRIC, "value": round(done_bytes / elapsed / 1e6, 3), "unit": "MB/s", "n_gpus": 1,
-        "steps": len(lat), "warmup": args.warmup, "ms_per_step": round(elapsed / len(lat) * 1e3, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"served-poisson-{args.qps}qps-{args.requests}req", "big_requests": len(big_ids),
-                   "tier": 4, "q_max": 6, "status": status},
-        "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 3),
-                       "p99": round(float(np.percentile(lat_ms, 99)), 3)},
+        "metric": METRIC, "value": head["value"], "unit": "MB/s", "n_gpus": 1, "steps": n,
+        "warmup": args.warmup, "ms_per_step": round(head["wall_s"] / n * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"served-poisson-{n}req-5pct-384cubed", "requests": n, "big_requests": n_big,
+                   "tier": 4, "q_max": 6, "plain_capacity_rps": round(capacity, 3),
+                   "plain_back_to_back": {"value": round(total_bytes / cap_s / 1e6, 3), "unit": "MB/s",
+                                          "wall_s": round(cap_s, 3)}},
+        "latency_ms": {"p50": head["p50_ms"], "p99": head["p99_ms"]},
+        "loads": runs,
     }
     print(json.dumps(line), flush=True)
+    ctx.close()
 
 
 def main():
@@ -268,7 +326,6 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="large2d", choices=["large2d", "small2d", "atoms3d", "batch64", "served"])
     ap.add_argument("--requests", type=int, default=200, help="served: requests in the stream")
-    ap.add_argument("--qps", type=float, default=4.0, help="served: Poisson arrival rate (requests/s)")
     ap.add_argument("--cpu-sample-iters", type=int, default=40,
                     help="iterations of the oracle timed on the full input for the CPU baseline")
     ap.add_argument("--no-extra-configs", action="store_true",

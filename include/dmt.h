@@ -166,6 +166,24 @@ dmt_status dmt_extract_msc(dmt_context *ctx, const dmt_grid *grid, const float *
 /* Copies item of the last extraction into dst (device, cap int64 entries). */
 dmt_status dmt_msc_copy(dmt_context *ctx, int item, int64_t *dst, int64_t cap, hipStream_t stream);
 
+/* Agreement of the MSC of g with that of f (Section 5.1, "Evaluation Metrics": critical and
+ * separatrix recall = common / f's, precision = common / g's).  All counts are of the complexes
+ * as dmt_extract_msc defines them:
+ *   crit_f[d], crit_g[d]  critical d-cells of f and of g (0 above the grid's dimension);
+ *   crit_common[d]        d-cells critical in both;
+ *   sep_f[k], sep_g[k]    separatrix branches, k = 0 descending (1-saddle -> minimum), k = 1
+ *                         ascending ((n-1)-saddle -> maximum or boundary);
+ *   sep_same_ends[k]      branches of f whose counterpart in g (same saddle, same first cell)
+ *                         ends at the same extremum (connectivity, tier 3);
+ *   sep_same_cells[k]     those whose whole cell sequence is equal (geometry, tier 4).
+ * f, g: N floats on the device.  Results on the host; the call synchronises the stream. */
+typedef struct {
+    int64_t crit_f[4], crit_g[4], crit_common[4];
+    int64_t sep_f[2], sep_g[2], sep_same_ends[2], sep_same_cells[2];
+} dmt_msc_agreement;
+dmt_status dmt_compare_msc(dmt_context *ctx, const dmt_grid *grid, const float *f, const float *g,
+                           dmt_msc_agreement *agreement_host, hipStream_t stream);
+
 /* ---- correction (Sections 4.2-4.7) ------------------------------------------------------- */
 
 /* Runs the C-loop / S-loop correction until f's MSC (at the requested tier) is restored.
@@ -260,12 +278,16 @@ int64_t dmt_workspace_bytes(const dmt_grid *grid, const dmt_options *opts);
 
 typedef struct dmt_server dmt_server;
 
-/* Starts a server on HIP device hip_device: a worker thread with its own context and stream.
- * Jobs are admitted in submission order while the summed workspace estimates of the jobs in
- * flight stay within hbm_budget_bytes (a job always starts on an idle server) and at most
- * max_jobs (1..4096) are in flight.  Admitted jobs are set up and then advance together in
- * rounds of one loop launch (at most 512 iterations per job), so later jobs join at the next
- * round and finished ones leave after theirs.  Each job's results equal those of dmt_correct. */
+/* Starts a server on HIP device hip_device: min(max_jobs, 4) worker lanes, each a thread with its
+ * own context and stream, among which the max_jobs slots (1..4096) are dealt out.  Jobs are
+ * admitted in submission order while the summed footprints of all jobs in flight (the larger of
+ * a job's estimate and the workspace it holds, plus what idle slots still hold) stay within
+ * hbm_budget_bytes; a job always starts on an idle server.  An idle lane takes the next queued job
+ * at once, so a job that arrives while others run starts on another stream and overlaps them on
+ * the device; a busy lane admits more only when every lane is busy.  Each lane advances its jobs
+ * together in rounds of one loop launch (at most 512 iterations per job), so its later jobs join
+ * at the next round and finished ones leave after theirs.  Each job's results equal those of
+ * dmt_correct. */
 dmt_status dmt_server_create(dmt_server **srv, int hip_device, int64_t hbm_budget_bytes, int32_t max_jobs);
 
 /* Waits for every submitted job to finish, then stops the worker and frees the server. */
@@ -319,6 +341,32 @@ dmt_status dmt_iteration_log(dmt_context *ctx, int64_t *log_host, int64_t cap, i
 dmt_status dmt_apply_edits(dmt_context *ctx, const float *g_hat, const uint8_t *q, int64_t n,
                            const int64_t *idx, const float *val, int64_t n_lossless, float xi,
                            int32_t q_max, float *g_out, hipStream_t stream);
+
+/* ---- edit stream (Section 4.7, "Quantized Representation of Edits") ----------------------- */
+
+/* Bits per vertex of the edit stream for q_max (0..7): the least b with 2^b >= q_max + 2 (codes
+ * 0..q_max are edit counts, q_max + 1 marks a lossless vertex); q_max 6 -> 3.  -1 for a bad q_max. */
+int32_t dmt_edit_bits(int32_t q_max);
+
+/* Encodes a correction's edits as the paper's fixed-bit stream: code k = q_out[k] (0xFF -> q_max + 1)
+ * in bits [k*b, (k+1)*b) of stream, little-endian within uint32 words (stream: device, at least
+ * ceil(n*b/32) words, unused high bits of the last word zero), and the values g_out[k] of the
+ * lossless vertices in vertex order into lossless_val (device, lossless_cap floats; no index is
+ * stored, the stream marks the positions).  n_lossless_host receives their number; with
+ * lossless_cap == 0 only the stream and the count are written, otherwise lossless_cap must be >= the
+ * count.  DMT_E_INVALID for q_out entries above q_max other than 0xFF.  Synchronises the stream.
+ * The stream is what a dictionary coder compresses next (the paper uses ZSTD). */
+dmt_status dmt_pack_edits(dmt_context *ctx, const uint8_t *q_out, const float *g_out, int64_t n, int32_t q_max,
+                          uint32_t *stream, int64_t stream_words, float *lossless_val, int64_t lossless_cap,
+                          int64_t *n_lossless_host, hipStream_t stream_hip);
+
+/* Decoder of dmt_pack_edits (decompression side of Section 4.7): g_out[k] = g_hat[k] - q * xi/2^q_max
+ * rounded once for codes q <= q_max, else the next lossless value; q_out (device, optional) gets
+ * the edit counts as dmt_correct wrote them.  DMT_E_INVALID for codes above q_max + 1 or a lossless
+ * count different from n_lossless.  Synchronises the stream. */
+dmt_status dmt_unpack_edits(dmt_context *ctx, const uint32_t *stream, int64_t stream_words, int64_t n,
+                            int32_t q_max, const float *g_hat, const float *lossless_val, int64_t n_lossless,
+                            float xi, float *g_out, uint8_t *q_out, hipStream_t stream_hip);
 
 /* ---- kernel timing (roofline measurement) ------------------------------------------------ */
 

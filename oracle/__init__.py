@@ -174,6 +174,66 @@ def msc(cx: Complex, h) -> MSC:
         L.omsc_free(m)
 
 
+def _separatrices(saddle, offsets, cells, terminal) -> dict:
+    """{(saddle, first cell): (terminal, cell sequence)} for one branch family."""
+    out = {}
+    for b in range(len(saddle)):
+        seq = tuple(int(x) for x in cells[offsets[b]:offsets[b + 1]])
+        out[(int(saddle[b]), seq[0] if seq else -1)] = (int(terminal[b]), seq)
+    return out
+
+
+def msc_agreement(cx: Complex, f, g) -> dict:
+    """Counts behind the critical / separatrix recall and precision of Section 5.1, from the two
+    complexes: critical cells of f, of g and of both by dimension; separatrices of f and g by
+    family (0 descending, 1 ascending) and those of f whose counterpart in g (the separatrix of the
+    same saddle through the same first cell) ends at the same extremum, or follows the same cells."""
+    mf, mg = msc(cx, f), msc(cx, g)
+    out = {"crit_f": [0] * 4, "crit_g": [0] * 4, "crit_common": [0] * 4,
+           "sep_f": [0, 0], "sep_g": [0, 0], "sep_same_ends": [0, 0], "sep_same_cells": [0, 0]}
+    for d in range(cx.top + 1):
+        a, b = set(mf.crit[d].tolist()), set(mg.crit[d].tolist())
+        out["crit_f"][d], out["crit_g"][d], out["crit_common"][d] = len(a), len(b), len(a & b)
+    for k, fam in enumerate(("desc", "asc")):
+        sf = _separatrices(*(getattr(mf, f"{fam}_{x}") for x in ("saddle", "offsets", "cells", "terminal")))
+        sg = _separatrices(*(getattr(mg, f"{fam}_{x}") for x in ("saddle", "offsets", "cells", "terminal")))
+        out["sep_f"][k], out["sep_g"][k] = len(sf), len(sg)
+        for key, (term, seq) in sf.items():
+            if key in sg:
+                out["sep_same_ends"][k] += sg[key][0] == term
+                out["sep_same_cells"][k] += sg[key] == (term, seq)
+    return out
+
+
+def edit_bits(q_max: int) -> int:
+    """Bits per code of the edit stream: codes 0..q_max are edit counts, q_max + 1 marks a
+    lossless vertex, so the least b with 2^b >= q_max + 2."""
+    b = 1
+    while 2 ** b < q_max + 2:
+        b += 1
+    return b
+
+
+def pack_edits(q, q_max: int) -> np.ndarray:
+    """The fixed-bit edit stream of Section 4.7 as uint32 words: vertex k's code (q, or q_max + 1
+    where q == 0xFF) in bits [k*b, (k+1)*b), least significant bit first."""
+    q = np.asarray(q, dtype=np.uint8).reshape(-1)
+    b = edit_bits(q_max)
+    codes = np.where(q == 0xFF, q_max + 1, q).astype(np.uint32)
+    bits = ((codes[:, None] >> np.arange(b, dtype=np.uint32)[None, :]) & 1).astype(np.uint8).reshape(-1)
+    words = (len(bits) + 31) // 32
+    bits = np.concatenate([bits, np.zeros(words * 32 - len(bits), np.uint8)])
+    return np.packbits(bits, bitorder="little").view("<u4").copy()
+
+
+def unpack_edits(words, n: int, q_max: int) -> np.ndarray:
+    """Inverse of pack_edits: the q of n vertices (0xFF for the lossless code)."""
+    b = edit_bits(q_max)
+    bits = np.unpackbits(np.asarray(words, dtype="<u4").view(np.uint8), bitorder="little")[:n * b]
+    codes = (bits.reshape(n, b).astype(np.uint32) << np.arange(b, dtype=np.uint32)[None, :]).sum(1)
+    return np.where(codes == q_max + 1, 0xFF, codes).astype(np.uint8)
+
+
 def bounds(f, xi: float):
     f = _f32(f)
     lo = np.zeros_like(f)

@@ -12,6 +12,7 @@
 #include <cstring>
 #include <string>
 #include <vector>
+#include <atomic>
 #include <condition_variable>
 #include <deque>
 #include <mutex>
@@ -20,6 +21,8 @@
 
 #include "dmt.h"
 #include "dmt_frontier.h"
+#include "dmt_verify.h"
+#include "dmt_codec.h"
 
 using namespace dmt;
 
@@ -121,6 +124,8 @@ struct dmt_context {
     std::string err;
     std::vector<JobWs> ws;                 // one workspace per job of the last batch (ws[0]: single calls)
     MscBufs msc;                           // results of dmt_extract_msc
+    MscBufs cmp[2];                        // the two complexes of dmt_compare_msc
+    DevBuf gpl2, agree;                    // dmt_compare_msc: second field's planes, counters
     DevBuf gpl, req, cnt, flags, part, blk, blkoff, ll_idx, ll_val, dlog, jobs_dev, ctl_all, queue, scan_tsum, scan_toff;
     int64_t n_lossless = 0;
     std::vector<int64_t> log;
@@ -1067,6 +1072,7 @@ dmt_status run_jobs(dmt_context* c, std::vector<Job>& jobs, bool single, hipStre
 namespace {
 
 constexpr int ROUND_PASSES = 512;
+constexpr int SERVER_LANES = 4;   // worker lanes of a server (streams whose jobs overlap on the device)
 
 int64_t workspace_estimate(int D, int64_t n) {
     // fields, state, f and g planes, frontier lists and stamps, separatrix branches (an upper
@@ -1093,33 +1099,44 @@ struct Ticket {
     dmt_job job{};
     Job J;
     int64_t bytes = 0;
+    int lane = -1;
     int state = 0;          // 0 pending, 1 active, 2 done
+};
+
+// One lane of the server: a worker thread with its own context (workspaces for its slots) and
+// stream.  Lanes run side by side, so a job admitted by an idle lane starts while other lanes'
+// jobs are on the device.
+struct Lane {
+    dmt_context* c = nullptr;
+    hipStream_t st = nullptr;
+    std::thread worker;
+    std::vector<int> free_slots;
+    // HBM accounting: charge[slot] = bytes the slot is counted for (an active job: the larger of
+    // its estimate and what its workspace holds; an idle slot: what its workspace still holds)
+    std::vector<int64_t> charge;
+    std::vector<int64_t> held;      // bytes each slot's workspace held when last accounted
+    int64_t shared = 0;             // the lane context's shared buffers
+    bool busy = false;              // holds admitted or active jobs
 };
 
 }  // namespace
 
 struct dmt_server {
-    dmt_context* c = nullptr;
-    hipStream_t st = nullptr;
+    std::vector<Lane> lanes;
     int64_t budget = 0;
     int max_jobs = 0;
-    std::thread worker;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     bool stop = false;
     std::unordered_map<int64_t, Ticket> tickets;
     std::deque<int64_t> pending;
-    std::vector<int> free_slots;
     int64_t next_ticket = 1;
-    // HBM accounting: charge[slot] = bytes the slot is counted for (an active job: the larger of
-    // its estimate and what its workspace holds; an idle slot: what its workspace still holds);
-    // inflight = sum of the charges plus the context's shared buffers
-    std::vector<int64_t> charge;
-    std::vector<int64_t> held;      // bytes each slot's workspace held when last accounted
-    int64_t shared = 0;
-    int64_t inflight = 0;
+    uint64_t epoch = 0;             // bumped when a job is submitted or finishes
+    int jobs_in_flight = 0;
+    int idle_lanes = 0;
+    int64_t inflight = 0;           // sum over lanes of their charges and shared buffers
     int64_t fail_outputs_at = -1;   // fault injection for tests: the k-th finished job's outputs fail
-    int64_t finished = 0;
+    std::atomic<int64_t> finished{0};
 };
 
 namespace {
@@ -1132,43 +1149,51 @@ int64_t shared_bytes(dmt_context* c) {
     return s;
 }
 
-// Recomputes inflight from the charges (caller holds s->mu).
+// Recomputes inflight from every lane's charges (caller holds s->mu).
 void recount(dmt_server* s) {
-    int64_t t = s->shared;
-    for (int64_t b : s->charge) t += b;
+    int64_t t = 0;
+    for (const Lane& L : s->lanes) {
+        t += L.shared;
+        for (int64_t b : L.charge) t += b;
+    }
     s->inflight = t;
 }
 
 // Ends a ticket that is no longer in any worker list.  The slot keeps its workspace for the next
 // job; its charge drops to what the workspace holds.
-void server_finish(dmt_server* s, Ticket& t, dmt_status status) {
-    const int64_t held = held_bytes(s->c->ws[t.J.slot]);
+void server_finish(dmt_server* s, Lane& L, Ticket& t, dmt_status status) {
+    const int64_t held = held_bytes(L.c->ws[t.J.slot]);
+    const int64_t shared = shared_bytes(L.c);
     std::lock_guard<std::mutex> lk(s->mu);
     t.job.status = status;
     t.job.stats = t.J.stats;
     t.state = 2;
-    s->charge[t.J.slot] = held;
-    s->held[t.J.slot] = held;
-    s->shared = shared_bytes(s->c);
+    L.charge[t.J.slot] = held;
+    L.held[t.J.slot] = held;
+    L.shared = shared;
     recount(s);
-    s->free_slots.push_back(t.J.slot);
+    L.free_slots.push_back(t.J.slot);
+    s->jobs_in_flight--;
+    s->epoch++;
     s->cv_done.notify_all();
+    s->cv_work.notify_all();
 }
 
 // Setup, f's gradient and branches, frontier state and iteration 0 of newly admitted jobs.  Each
 // ticket leaves `admit` when it is finished (validation failure) or moved to `active`; on an
 // error the tickets still in `admit` have not been finished.
-dmt_status server_admit(dmt_server* s, std::vector<Ticket*>& admit, std::vector<Ticket*>& active) {
-    dmt_context* c = s->c;
-    const hipStream_t st = s->st;
-    HIPCHK(c, hipMemsetAsync(c->flags.p, 0, sizeof(unsigned) * (s->max_jobs + 1), st));
+dmt_status server_admit(dmt_server* s, Lane& L, std::vector<Ticket*>& admit, std::vector<Ticket*>& active) {
+    dmt_context* c = L.c;
+    const hipStream_t st = L.st;
+    const int nslots = (int)L.charge.size();
+    HIPCHK(c, hipMemsetAsync(c->flags.p, 0, sizeof(unsigned) * (nslots + 1), st));
     for (Ticket* t : admit) {
         Job& J = t->J;
         J.w = &c->ws[J.slot];
         unsigned* flag = P<unsigned>(c->flags) + 1 + J.slot;
         TRY(J.D == 2 ? job_setup<2>(c, J, flag, st) : job_setup<3>(c, J, flag, st));
     }
-    std::vector<unsigned> fl(s->max_jobs + 1);
+    std::vector<unsigned> fl(nslots + 1);
     HIPCHK(c, hipMemcpyAsync(fl.data(), c->flags.p, sizeof(unsigned) * fl.size(), hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));
     while (!admit.empty()) {
@@ -1177,7 +1202,7 @@ dmt_status server_admit(dmt_server* s, std::vector<Ticket*>& admit, std::vector<
         const unsigned f = fl[1 + J.slot];
         if (f & 3u) {
             admit.erase(admit.begin());
-            server_finish(s, *t, (f & 1u) ? DMT_E_NONFINITE : DMT_E_BOUND);
+            server_finish(s, L, *t, (f & 1u) ? DMT_E_NONFINITE : DMT_E_BOUND);
             continue;
         }
         Ctl* ctl = P<Ctl>(c->ctl_all) + J.slot;
@@ -1187,22 +1212,23 @@ dmt_status server_admit(dmt_server* s, std::vector<Ticket*>& admit, std::vector<
         active.push_back(t);
         // the separatrix buffers are data-dependent: charge what the job holds once they exist
         const int64_t held = held_bytes(c->ws[J.slot]);
+        const int64_t shared = shared_bytes(c);
         std::lock_guard<std::mutex> lk(s->mu);
-        s->charge[J.slot] = std::max(t->bytes, held);
-        s->held[J.slot] = held;
-        s->shared = shared_bytes(c);
+        L.charge[J.slot] = std::max(t->bytes, held);
+        L.held[J.slot] = held;
+        L.shared = shared;
         recount(s);
     }
     return DMT_OK;
 }
 
-// One round of the active jobs; finished ones get their outputs and leave `active` before they
-// are handed back.
-dmt_status server_round(dmt_server* s, std::vector<Ticket*>& active) {
-    dmt_context* c = s->c;
+// One round of the lane's active jobs; finished ones get their outputs and leave `active` before
+// they are handed back.
+dmt_status server_round(dmt_server* s, Lane& L, std::vector<Ticket*>& active) {
+    dmt_context* c = L.c;
     std::vector<Job*> js;
     for (Ticket* t : active) js.push_back(&t->J);
-    TRY(run_wg(c, js, false, s->st, 1, ROUND_PASSES));
+    TRY(run_wg(c, js, false, L.st, 1, ROUND_PASSES));
     for (size_t i = 0; i < active.size();) {
         Ticket* t = active[i];
         const Ctl h = c->hctl[t->J.slot];
@@ -1212,70 +1238,96 @@ dmt_status server_round(dmt_server* s, std::vector<Ticket*>& active) {
         }
         active.erase(active.begin() + (long)i);
         dmt_status rc = DMT_OK;
-        if (s->fail_outputs_at >= 0 && s->finished++ == s->fail_outputs_at)
+        if (s->fail_outputs_at >= 0 && s->finished.fetch_add(1) == s->fail_outputs_at)
             rc = fail(c, DMT_E_NOMEM, "injected output failure");
         else
-            rc = job_outputs(c, t->J, h, false, s->st);
-        server_finish(s, *t, rc == DMT_OK ? t->J.status : rc);
+            rc = job_outputs(c, t->J, h, false, L.st);
+        server_finish(s, L, *t, rc == DMT_OK ? t->J.status : rc);
         if (rc != DMT_OK) return rc;
     }
     return DMT_OK;
 }
 
-// Admission by footprint (caller holds s->mu): the job at the head of the queue is admitted if a
-// slot is free and the accounted bytes stay within the budget, after releasing the workspaces of
-// idle slots if that is what it takes; the first job always fits an idle server.
-bool server_try_admit(dmt_server* s, Ticket& t, bool idle) {
-    if (s->free_slots.empty()) return false;
+// Admission by footprint (caller holds s->mu): the job at the head of the queue is admitted to a
+// free slot of lane L if the accounted bytes of all lanes stay within the budget, after releasing
+// the workspaces of L's idle slots if that is what it takes; a job always fits an idle server.
+bool server_try_admit(dmt_server* s, Lane& L, Ticket& t) {
+    if (L.free_slots.empty()) return false;
+    const bool idle = s->jobs_in_flight == 0;
     // prefer the idle slot holding the most memory already (its buffers are reused)
     int best = -1;
-    for (size_t k = 0; k < s->free_slots.size(); k++)
-        if (best < 0 || s->charge[s->free_slots[k]] > s->charge[s->free_slots[best]]) best = (int)k;
-    const int slot = s->free_slots[best];
-    auto need = [&] { return s->inflight - s->charge[slot] + std::max(t.bytes, s->charge[slot]); };
+    for (size_t k = 0; k < L.free_slots.size(); k++)
+        if (best < 0 || L.charge[L.free_slots[k]] > L.charge[L.free_slots[best]]) best = (int)k;
+    const int slot = L.free_slots[best];
+    auto need = [&] { return s->inflight - L.charge[slot] + std::max(t.bytes, L.charge[slot]); };
     if (need() > s->budget) {
-        // give back what other idle slots hold
-        for (int k : s->free_slots) {
-            if (k == slot || s->charge[k] == 0) continue;
-            release(s->c->ws[k]);
-            s->charge[k] = 0;
-            s->held[k] = 0;
+        // give back what the lane's other idle slots hold (this lane's worker owns them)
+        for (int k : L.free_slots) {
+            if (k == slot || L.charge[k] == 0) continue;
+            release(L.c->ws[k]);
+            L.charge[k] = 0;
+            L.held[k] = 0;
         }
         recount(s);
     }
     if (need() > s->budget && !idle) return false;
-    s->free_slots.erase(s->free_slots.begin() + best);
+    L.free_slots.erase(L.free_slots.begin() + best);
     t.J.slot = slot;
-    s->charge[slot] = std::max(t.bytes, s->charge[slot]);
+    L.charge[slot] = std::max(t.bytes, L.charge[slot]);
     recount(s);
     t.state = 1;
+    s->jobs_in_flight++;
     return true;
 }
 
-void server_main(dmt_server* s) {
-    (void)hipSetDevice(s->c->device);
+void server_main(dmt_server* s, int li) {
+    Lane& L = s->lanes[li];
+    (void)hipSetDevice(L.c->device);
     std::vector<Ticket*> active;
+    uint64_t seen = ~0ull;   // epoch of an idle lane's last admission attempt that took nothing
     for (;;) {
         std::vector<Ticket*> admit;
         {
             std::unique_lock<std::mutex> lk(s->mu);
-            s->cv_work.wait(lk, [&] { return s->stop || !s->pending.empty() || !active.empty(); });
-            if (s->stop && s->pending.empty() && active.empty()) break;
-            while (!s->pending.empty()) {
-                Ticket& t = s->tickets.at(s->pending.front());
-                if (!server_try_admit(s, t, active.empty() && admit.empty())) break;
-                admit.push_back(&t);
-                s->pending.pop_front();
+            if (active.empty()) {
+                s->cv_work.wait(lk, [&] {
+                    return (s->stop && s->pending.empty()) || (!s->pending.empty() && s->epoch != seen);
+                });
+                if (s->pending.empty()) break;   // stopping, nothing left
+            }
+            // idle lanes take new jobs first; a busy lane admits more only when every lane is busy
+            if (active.empty() || s->idle_lanes == 0) {
+                while (!s->pending.empty()) {
+                    Ticket& t = s->tickets.at(s->pending.front());
+                    if (!server_try_admit(s, L, t)) break;
+                    t.lane = li;
+                    admit.push_back(&t);
+                    s->pending.pop_front();
+                }
+            }
+            if (active.empty() && admit.empty()) {
+                seen = s->epoch;
+                continue;
+            }
+            if (!L.busy) {
+                L.busy = true;
+                s->idle_lanes--;
             }
         }
         dmt_status rc = DMT_OK;
-        if (!admit.empty()) rc = server_admit(s, admit, active);
-        if (rc == DMT_OK && !active.empty()) rc = server_round(s, active);
+        if (!admit.empty()) rc = server_admit(s, L, admit, active);
+        if (rc == DMT_OK && !active.empty()) rc = server_round(s, L, active);
         if (rc != DMT_OK) {
-            // a failure ends every job still held by the worker with that status
-            for (Ticket* t : active) server_finish(s, *t, rc);
-            for (Ticket* t : admit) server_finish(s, *t, rc);
+            // a failure ends every job still held by this lane with that status
+            for (Ticket* t : active) server_finish(s, L, *t, rc);
+            for (Ticket* t : admit) server_finish(s, L, *t, rc);
             active.clear();
+        }
+        if (active.empty()) {
+            std::lock_guard<std::mutex> lk(s->mu);
+            L.busy = false;
+            s->idle_lanes++;
+            seen = ~0ull;
         }
     }
 }
@@ -1310,6 +1362,10 @@ dmt_status dmt_context_destroy(dmt_context* c) {
     (void)hipSetDevice(c->device);
     std::vector<DevBuf*> bufs = context_bufs(c);
     for (DevBuf* b : c->msc.all()) bufs.push_back(b);
+    for (MscBufs& m : c->cmp)
+        for (DevBuf* b : m.all()) bufs.push_back(b);
+    bufs.push_back(&c->gpl2);
+    bufs.push_back(&c->agree);
     for (JobWs& w : c->ws)
         for (DevBuf* b : w.all()) bufs.push_back(b);
     for (DevBuf* b : bufs)
@@ -1415,6 +1471,64 @@ dmt_status dmt_extract_msc(dmt_context* c, const dmt_grid* gr, const float* fiel
     counts[DMT_MSC_ASC_TERMINAL] = m.n_asc;
     counts[DMT_MSC_MIN_LABEL] = m.n_vlab;
     counts[DMT_MSC_MAX_LABEL] = m.n_tlab;
+    return DMT_OK;
+}
+
+dmt_status dmt_compare_msc(dmt_context* c, const dmt_grid* gr, const float* f, const float* g,
+                           dmt_msc_agreement* out, hipStream_t st) {
+    if (!c || !f || !g || !out) return fail(c, DMT_E_INVALID, "null argument");
+    Dims dm;
+    int D;
+    TRY(check_grid(c, gr, dm, D));
+    HIPCHK(c, hipSetDevice(c->device));
+    const size_t planes = (size_t)nplanes(D) * dm.n;
+    ENSURE(c, c->gpl, planes);
+    ENSURE(c, c->gpl2, planes);
+    TRY(launch_grad(c, D, f, P<uint8_t>(c->gpl), dm, st));
+    TRY(launch_grad(c, D, g, P<uint8_t>(c->gpl2), dm, st));
+    MscBufs& mf = c->cmp[0];
+    MscBufs& mg = c->cmp[1];
+    TRY(D == 2 ? build_msc<2>(c, mf, P<uint8_t>(c->gpl), dm, false, st)
+               : build_msc<3>(c, mf, P<uint8_t>(c->gpl), dm, false, st));
+    TRY(D == 2 ? build_msc<2>(c, mg, P<uint8_t>(c->gpl2), dm, false, st)
+               : build_msc<3>(c, mg, P<uint8_t>(c->gpl2), dm, false, st));
+    constexpr int NW = 8;   // counters: common critical cells by dimension, then (ends, cells) per family
+    ENSURE(c, c->agree, sizeof(unsigned long long) * NW);
+    unsigned long long* cnt = P<unsigned long long>(c->agree);
+    HIPCHK(c, hipMemsetAsync(cnt, 0, sizeof(unsigned long long) * NW, st));
+    for (int d = 0; d <= D; d++)
+        if (mf.ncrit[d] && mg.ncrit[d]) {
+            k_count_common<<<nblocks(mf.ncrit[d]), TPB, 0, st>>>(P<int>(mf.crit[d]), mf.ncrit[d], P<int>(mg.crit[d]),
+                                                                 mg.ncrit[d], cnt + d);
+            CHECK_LAUNCH(c);
+        }
+    auto desc = [](MscBufs& m) {
+        return BranchList{nullptr, P<int>(m.crit[1]), P<int64_t>(m.doff), P<int>(m.dcell), P<int>(m.dterm), m.n_desc};
+    };
+    auto asc = [](MscBufs& m) {
+        return BranchList{P<int>(m.asad), nullptr, P<int64_t>(m.aoff), P<int>(m.acell), P<int>(m.aterm), m.n_asc};
+    };
+    if (mf.n_desc && mg.n_desc) {
+        k_branch_agree<<<nblocks(mf.n_desc * 64), TPB, 0, st>>>(desc(mf), desc(mg), cnt + 4);
+        CHECK_LAUNCH(c);
+    }
+    if (mf.n_asc && mg.n_asc) {
+        k_branch_agree<<<nblocks(mf.n_asc * 64), TPB, 0, st>>>(asc(mf), asc(mg), cnt + 6);
+        CHECK_LAUNCH(c);
+    }
+    HIPCHK(c, hipMemcpyAsync(c->hscratch, cnt, sizeof(unsigned long long) * NW, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    const int64_t* h = c->hscratch;
+    *out = dmt_msc_agreement{};
+    for (int d = 0; d < 4; d++) {
+        out->crit_f[d] = mf.ncrit[d];
+        out->crit_g[d] = mg.ncrit[d];
+        out->crit_common[d] = d <= D ? h[d] : 0;
+    }
+    out->sep_f[0] = mf.n_desc; out->sep_g[0] = mg.n_desc;
+    out->sep_f[1] = mf.n_asc;  out->sep_g[1] = mg.n_asc;
+    out->sep_same_ends[0] = h[4]; out->sep_same_cells[0] = h[5];
+    out->sep_same_ends[1] = h[6]; out->sep_same_cells[1] = h[7];
     return DMT_OK;
 }
 
@@ -1696,6 +1810,80 @@ dmt_status dmt_apply_edits(dmt_context* c, const float* g_hat, const uint8_t* q,
 }
 
 
+int32_t dmt_edit_bits(int32_t q_max) { return q_max < 0 || q_max > 7 ? -1 : edit_bits(q_max); }
+
+dmt_status dmt_pack_edits(dmt_context* c, const uint8_t* q_out, const float* g_out, int64_t n, int32_t q_max,
+                          uint32_t* stream, int64_t stream_words, float* lossless_val, int64_t lossless_cap,
+                          int64_t* n_lossless, hipStream_t st) {
+    if (!c || !q_out || !g_out || !stream || !n_lossless || n < 0 || lossless_cap < 0)
+        return fail(c, DMT_E_INVALID, "bad argument");
+    if (q_max < 0 || q_max > 7) return fail(c, DMT_E_INVALID, "q_max must be 0..7");
+    if (n > (int64_t)INT32_MAX) return fail(c, DMT_E_INVALID, "too many vertices");
+    const int b = edit_bits(q_max);
+    const int64_t words = (n * b + 31) / 32;
+    if (stream_words < words) return fail(c, DMT_E_INVALID, "stream too small: needs " + std::to_string((long long)words) +
+                                                               " words");
+    *n_lossless = 0;
+    if (n == 0) return DMT_OK;
+    HIPCHK(c, hipSetDevice(c->device));
+    const unsigned nb = nblocks(n);
+    ENSURE(c, c->flags, 16);
+    ENSURE(c, c->blk, sizeof(int) * (size_t)nb);
+    ENSURE(c, c->blkoff, sizeof(int64_t) * (size_t)(nb + 1));
+    HIPCHK(c, hipMemsetAsync(c->flags.p, 0, sizeof(unsigned), st));
+    k_pack_edits<<<nblocks(words), TPB, 0, st>>>(q_out, n, q_max, b, words, stream, P<unsigned>(c->flags));
+    k_lossless_count<<<nb, TPB, 0, st>>>(q_out, (int)n, P<int>(c->blk));
+    CHECK_LAUNCH(c);
+    int64_t total = 0;
+    TRY(scan(c, P<int>(c->blk), nb, P<int64_t>(c->blkoff), &total, st));   // synchronises
+    HIPCHK(c, hipMemcpyAsync(c->hscratch, c->flags.p, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    if (*reinterpret_cast<unsigned*>(c->hscratch)) return fail(c, DMT_E_INVALID, "q_out holds a value above q_max");
+    *n_lossless = total;
+    if (total == 0 || lossless_cap == 0) return DMT_OK;
+    if (!lossless_val) return fail(c, DMT_E_INVALID, "null lossless_val");
+    if (lossless_cap < total) return fail(c, DMT_E_INVALID, "lossless_val too small");
+    k_lossless_write<<<nb, TPB, 0, st>>>(q_out, g_out, (int)n, P<int64_t>(c->blkoff), nullptr, lossless_val);
+    CHECK_LAUNCH(c);
+    HIPCHK(c, hipStreamSynchronize(st));
+    return DMT_OK;
+}
+
+dmt_status dmt_unpack_edits(dmt_context* c, const uint32_t* stream, int64_t stream_words, int64_t n, int32_t q_max,
+                            const float* g_hat, const float* lossless_val, int64_t n_lossless, float xi, float* g_out,
+                            uint8_t* q_out, hipStream_t st) {
+    if (!c || !stream || !g_hat || !g_out || n < 0 || n_lossless < 0) return fail(c, DMT_E_INVALID, "bad argument");
+    if (n_lossless && !lossless_val) return fail(c, DMT_E_INVALID, "null lossless_val");
+    if (q_max < 0 || q_max > 7) return fail(c, DMT_E_INVALID, "q_max must be 0..7");
+    if (!(xi > 0.0f) || !std::isfinite(xi) || !(ldexpf(xi, -q_max) >= FLT_MIN)) return fail(c, DMT_E_INVALID, "bad xi");
+    if (n > (int64_t)INT32_MAX) return fail(c, DMT_E_INVALID, "too many vertices");
+    const int b = edit_bits(q_max);
+    const int64_t words = (n * b + 31) / 32;
+    if (stream_words < words) return fail(c, DMT_E_INVALID, "stream too short for n vertices");
+    if (n == 0) return DMT_OK;
+    HIPCHK(c, hipSetDevice(c->device));
+    const unsigned nb = nblocks(n);
+    ENSURE(c, c->flags, 16);
+    ENSURE(c, c->blk, sizeof(int) * (size_t)nb);
+    ENSURE(c, c->blkoff, sizeof(int64_t) * (size_t)(nb + 1));
+    HIPCHK(c, hipMemsetAsync(c->flags.p, 0, sizeof(unsigned), st));
+    k_unpack_count<<<nb, TPB, 0, st>>>(stream, words, (int)n, q_max, b, P<int>(c->blk), P<unsigned>(c->flags));
+    CHECK_LAUNCH(c);
+    int64_t total = 0;
+    TRY(scan(c, P<int>(c->blk), nb, P<int64_t>(c->blkoff), &total, st));
+    HIPCHK(c, hipMemcpyAsync(c->hscratch, c->flags.p, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    if (*reinterpret_cast<unsigned*>(c->hscratch)) return fail(c, DMT_E_INVALID, "stream holds a code above q_max + 1");
+    if (total != n_lossless)
+        return fail(c, DMT_E_INVALID, "stream marks " + std::to_string((long long)total) + " lossless vertices, " +
+                                          std::to_string((long long)n_lossless) + " values given");
+    k_unpack_write<<<nb, TPB, 0, st>>>(stream, words, (int)n, q_max, b, g_hat, lossless_val, P<int64_t>(c->blkoff),
+                                       n_lossless, ldexpf(xi, -q_max), g_out, q_out, P<unsigned>(c->flags));
+    CHECK_LAUNCH(c);
+    HIPCHK(c, hipStreamSynchronize(st));
+    return DMT_OK;
+}
+
 int64_t dmt_workspace_bytes(const dmt_grid* gr, const dmt_options* o) {
     if (!gr || !o) return -1;
     Dims dm;
@@ -1708,32 +1896,44 @@ dmt_status dmt_server_create(dmt_server** out, int hip_device, int64_t hbm_budge
     if (!out || hbm_budget_bytes <= 0 || max_jobs < 1 || max_jobs > 4096) return DMT_E_INVALID;
     *out = nullptr;
     dmt_server* s = new dmt_server();
-    dmt_status rc = dmt_context_create(&s->c, hip_device);
+    s->budget = hbm_budget_bytes;
+    s->max_jobs = max_jobs;
+    // up to SERVER_LANES lanes; the max_jobs slots are dealt out among them
+    const int nl = std::min(max_jobs, SERVER_LANES);
+    s->lanes.resize(nl);
+    dmt_status rc = DMT_OK;
+    for (int li = 0; li < nl && rc == DMT_OK; li++) {
+        Lane& L = s->lanes[li];
+        const int nslots = max_jobs / nl + (li < max_jobs % nl ? 1 : 0);
+        rc = dmt_context_create(&L.c, hip_device);
+        if (rc != DMT_OK) break;
+        dmt_context* c = L.c;
+        c->ws.resize(nslots);
+        c->hctl.assign(nslots, Ctl{});
+        if (hipStreamCreateWithFlags(&L.st, hipStreamNonBlocking) != hipSuccess ||
+            ensure(c, c->ctl_all, sizeof(Ctl) * nslots) != DMT_OK ||
+            ensure(c, c->flags, sizeof(unsigned) * (nslots + 1)) != DMT_OK ||
+            hipMemsetAsync(c->ctl_all.p, 0, sizeof(Ctl) * nslots, L.st) != hipSuccess) {
+            rc = DMT_E_NOMEM;
+            break;
+        }
+        for (int k = nslots - 1; k >= 0; k--) L.free_slots.push_back(k);
+        L.charge.assign(nslots, 0);
+        L.held.assign(nslots, 0);
+        L.shared = shared_bytes(c);
+    }
     if (rc != DMT_OK) {
+        for (Lane& L : s->lanes) {
+            if (L.st) (void)hipStreamDestroy(L.st);
+            if (L.c) dmt_context_destroy(L.c);
+        }
         delete s;
         return rc;
     }
-    dmt_context* c = s->c;
-    s->budget = hbm_budget_bytes;
-    s->max_jobs = max_jobs;
-    c->ws.resize(max_jobs);
-    c->hctl.assign(max_jobs, Ctl{});
-    if (hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking) != hipSuccess ||
-        ensure(c, c->ctl_all, sizeof(Ctl) * max_jobs) != DMT_OK ||
-        ensure(c, c->flags, sizeof(unsigned) * (max_jobs + 1)) != DMT_OK ||
-        hipMemsetAsync(c->ctl_all.p, 0, sizeof(Ctl) * max_jobs, s->st) != hipSuccess) {
-        if (s->st) (void)hipStreamDestroy(s->st);
-        dmt_context_destroy(c);
-        delete s;
-        return DMT_E_NOMEM;
-    }
-    for (int k = max_jobs - 1; k >= 0; k--) s->free_slots.push_back(k);
-    s->charge.assign(max_jobs, 0);
-    s->held.assign(max_jobs, 0);
-    s->shared = shared_bytes(c);
     recount(s);
+    s->idle_lanes = nl;
     if (const char* e = getenv("DMT_FAULT_OUTPUTS")) s->fail_outputs_at = atoll(e);
-    s->worker = std::thread(server_main, s);
+    for (int li = 0; li < nl; li++) s->lanes[li].worker = std::thread(server_main, s, li);
     *out = s;
     return DMT_OK;
 }
@@ -1745,10 +1945,13 @@ dmt_status dmt_server_destroy(dmt_server* s) {
         s->stop = true;
     }
     s->cv_work.notify_all();
-    if (s->worker.joinable()) s->worker.join();
-    (void)hipSetDevice(s->c->device);
-    if (s->st) (void)hipStreamDestroy(s->st);
-    dmt_context_destroy(s->c);
+    for (Lane& L : s->lanes)
+        if (L.worker.joinable()) L.worker.join();
+    for (Lane& L : s->lanes) {
+        (void)hipSetDevice(L.c->device);
+        if (L.st) (void)hipStreamDestroy(L.st);
+        dmt_context_destroy(L.c);
+    }
     delete s;
     return DMT_OK;
 }
@@ -1772,6 +1975,7 @@ dmt_status dmt_server_submit(dmt_server* s, const dmt_job* job, int64_t* ticket)
         *ticket = s->next_ticket++;
         s->tickets.emplace(*ticket, std::move(t));
         s->pending.push_back(*ticket);
+        s->epoch++;
     }
     s->cv_work.notify_all();
     return DMT_OK;
@@ -1782,18 +1986,20 @@ dmt_status dmt_server_info(dmt_server* s, int64_t* inflight_bytes, int64_t* held
     if (!s) return DMT_E_INVALID;
     std::lock_guard<std::mutex> lk(s->mu);
     if (inflight_bytes) *inflight_bytes = s->inflight;
-    if (held_bytes_host) {
-        int64_t h = s->shared;
-        for (int64_t b : s->held) h += b;
-        *held_bytes_host = h;
-    }
-    if (free_slots) *free_slots = (int32_t)s->free_slots.size();
-    if (pending) *pending = (int32_t)s->pending.size();
-    if (distinct_free_slots) {
-        std::vector<int> v = s->free_slots;
+    int64_t h = 0;
+    int32_t nfree = 0, ndistinct = 0;
+    for (const Lane& L : s->lanes) {
+        h += L.shared;
+        for (int64_t b : L.held) h += b;
+        nfree += (int32_t)L.free_slots.size();
+        std::vector<int> v = L.free_slots;
         std::sort(v.begin(), v.end());
-        *distinct_free_slots = (int32_t)(std::unique(v.begin(), v.end()) - v.begin());
+        ndistinct += (int32_t)(std::unique(v.begin(), v.end()) - v.begin());
     }
+    if (held_bytes_host) *held_bytes_host = h;
+    if (free_slots) *free_slots = nfree;
+    if (pending) *pending = (int32_t)s->pending.size();
+    if (distinct_free_slots) *distinct_free_slots = ndistinct;
     return DMT_OK;
 }
 

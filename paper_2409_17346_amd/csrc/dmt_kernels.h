@@ -539,7 +539,7 @@ __global__ void __launch_bounds__(256) k_lossless_write(const uint8_t* __restric
     const int off = block_exclusive_scan(ll, tot);
     if (ll) {
         const int64_t k = blk_off[blockIdx.x] + off;
-        idx[k] = v;
+        if (idx) idx[k] = v;
         val[k] = g[v];
     }
 }

@@ -45,7 +45,7 @@ ABI_SYMBOLS = [
     "dmt_correct", "dmt_correct_batch", "dmt_lossless_edits", "dmt_iteration_log", "dmt_apply_edits",
     "dmt_profile_enable", "dmt_profile_read", "dmt_workspace_bytes", "dmt_server_create", "dmt_server_destroy",
     "dmt_server_submit", "dmt_server_poll", "dmt_server_info", "dmt_lossless_list", "dmt_correct_noalloc",
-    "dmt_set_tuning", "dmt_get_tuning",
+    "dmt_set_tuning", "dmt_get_tuning", "dmt_compare_msc", "dmt_edit_bits", "dmt_pack_edits", "dmt_unpack_edits",
 ]
 
 PROF_KERNELS = {"gradient": 0, "classify": 1, "apply": 2, "sstep": 3, "setup": 4, "msc": 5, "loop": 6,
@@ -81,6 +81,12 @@ class dmt_tuning(C.Structure):
 
     def as_dict(self) -> Dict[str, list]:
         return {k: list(getattr(self, k)) for k, _ in self._fields_}
+
+
+class dmt_msc_agreement(C.Structure):
+    _fields_ = [("crit_f", C.c_int64 * 4), ("crit_g", C.c_int64 * 4), ("crit_common", C.c_int64 * 4),
+                ("sep_f", C.c_int64 * 2), ("sep_g", C.c_int64 * 2), ("sep_same_ends", C.c_int64 * 2),
+                ("sep_same_cells", C.c_int64 * 2)]
 
 
 class dmt_job(C.Structure):
@@ -128,6 +134,12 @@ def load_library(path: str = SO):
     P32 = C.POINTER(C.c_int32)
     L.dmt_server_info.argtypes = [VP, P64, P64, P32, P32, P32]
     L.dmt_lossless_list.argtypes = [VP, VP, VP, C.c_int64, VP, VP, C.c_int64, P64, VP]
+    L.dmt_compare_msc.argtypes = [VP, C.POINTER(dmt_grid), VP, VP, C.POINTER(dmt_msc_agreement), VP]
+    L.dmt_edit_bits.argtypes = [C.c_int32]
+    L.dmt_edit_bits.restype = C.c_int32
+    L.dmt_pack_edits.argtypes = [VP, VP, VP, C.c_int64, C.c_int32, VP, C.c_int64, VP, C.c_int64, P64, VP]
+    L.dmt_unpack_edits.argtypes = [VP, VP, C.c_int64, C.c_int64, C.c_int32, VP, VP, C.c_int64, C.c_float, VP, VP,
+                                   VP]
     L.dmt_set_tuning.argtypes = [VP, C.POINTER(dmt_tuning)]
     L.dmt_get_tuning.argtypes = [VP, C.POINTER(dmt_tuning)]
     L.dmt_correct_noalloc.argtypes = [VP, C.POINTER(dmt_grid), VP, VP, C.c_float, C.POINTER(dmt_options), VP, VP,
@@ -136,6 +148,7 @@ def load_library(path: str = SO):
         if name != "dmt_last_error":
             getattr(L, name).restype = C.c_int
     L.dmt_workspace_bytes.restype = C.c_int64
+    L.dmt_edit_bits.restype = C.c_int32
     _lib = L
     return L
 
@@ -285,6 +298,98 @@ def dmt_correct(ctx: Context, f: torch.Tensor, g_hat: torch.Tensor, xi: float, t
         idx, val = dmt_lossless_edits(ctx, f.device)
         log = dmt_iteration_log(ctx)
     return Result(STATUS_NAMES[rc], g_out, q_out, stats, idx, val, log)
+
+
+def dmt_compare_msc(ctx: Context, f: torch.Tensor, g: torch.Tensor) -> Dict[str, object]:
+    """Agreement of g's MSC with f's (Section 5.1): the raw counts of dmt_msc_agreement plus
+    critical and separatrix recall / precision (separatrices: identical cell sequences; the
+    *_connectivity variants: same saddle, same first cell, same terminal)."""
+    _dev(f)
+    _dev(g)
+    if f.shape != g.shape:
+        raise ValueError("f and g differ in shape")
+    a = dmt_msc_agreement()
+    ctx.check(ctx.L.dmt_compare_msc(ctx.h, C.byref(grid_of(f)), VP(f.data_ptr()), VP(g.data_ptr()), C.byref(a),
+                                    _stream(f)))
+    out = {k: list(getattr(a, k)) for k, _ in a._fields_}
+    return dict(out, **agreement_rates(out))
+
+
+def agreement_rates(a: Dict[str, list]) -> Dict[str, float]:
+    """Recall (common / f's) and precision (common / g's) from agreement counts; 1.0 for empty sets."""
+    def ratio(x, y):
+        return 1.0 if y == 0 else x / y
+    cc, cf, cg = sum(a["crit_common"]), sum(a["crit_f"]), sum(a["crit_g"])
+    sc, se, sf, sg = sum(a["sep_same_cells"]), sum(a["sep_same_ends"]), sum(a["sep_f"]), sum(a["sep_g"])
+    return {"critical_recall": ratio(cc, cf), "critical_precision": ratio(cc, cg),
+            "separatrix_recall": ratio(sc, sf), "separatrix_precision": ratio(sc, sg),
+            "separatrix_recall_connectivity": ratio(se, sf), "separatrix_precision_connectivity": ratio(se, sg)}
+
+
+def dmt_edit_bits(q_max: int) -> int:
+    return int(load_library().dmt_edit_bits(q_max))
+
+
+def dmt_pack_edits(ctx: Context, q_out: torch.Tensor, g_out: torch.Tensor, q_max: int
+                   ) -> Tuple[torch.Tensor, torch.Tensor]:
+    """The fixed-bit edit stream (uint32 words) and the lossless values in vertex order."""
+    _dev(q_out, torch.uint8)
+    _dev(g_out)
+    n = q_out.numel()
+    b = dmt_edit_bits(q_max)
+    if b < 0:
+        raise ValueError("q_max must be 0..7")
+    words = (n * b + 31) // 32
+    stream = torch.empty(max(words, 1), dtype=torch.int32, device=q_out.device)
+    cnt = C.c_int64()
+    s = _stream(q_out)
+    ctx.check(ctx.L.dmt_pack_edits(ctx.h, VP(q_out.data_ptr()), VP(g_out.data_ptr()), n, q_max, VP(stream.data_ptr()),
+                                   words, None, 0, C.byref(cnt), s))
+    val = torch.empty(cnt.value, dtype=torch.float32, device=q_out.device)
+    if cnt.value:
+        ctx.check(ctx.L.dmt_pack_edits(ctx.h, VP(q_out.data_ptr()), VP(g_out.data_ptr()), n, q_max,
+                                       VP(stream.data_ptr()), words, VP(val.data_ptr()), cnt.value, C.byref(cnt), s))
+    return stream[:words], val
+
+
+def dmt_unpack_edits(ctx: Context, stream: torch.Tensor, lossless_val: torch.Tensor, g_hat: torch.Tensor, xi: float,
+                     q_max: int, want_q: bool = True) -> Tuple[torch.Tensor, Optional[torch.Tensor]]:
+    """Decoder of dmt_pack_edits: the corrected field (and the edit counts)."""
+    _dev(stream, torch.int32)
+    _dev(lossless_val)
+    _dev(g_hat)
+    g = torch.empty_like(g_hat)
+    q = torch.empty(g_hat.shape, dtype=torch.uint8, device=g_hat.device) if want_q else None
+    ctx.check(ctx.L.dmt_unpack_edits(ctx.h, VP(stream.data_ptr()), stream.numel(), g_hat.numel(), q_max,
+                                     VP(g_hat.data_ptr()), VP(lossless_val.data_ptr()), lossless_val.numel(), xi,
+                                     VP(g.data_ptr()), VP(q.data_ptr()) if want_q else None, _stream(g_hat)))
+    return g, q
+
+
+def compress_edits(stream: torch.Tensor, lossless_val: torch.Tensor, level: int = 9) -> bytes:
+    """The dictionary-coder stage on the host: DEFLATE (zlib) of the edit stream followed by the
+    lossless values, standing in for the paper's ZSTD (not available here).  Layout: uint64 stream
+    words, uint64 lossless count, the two compressed sections' lengths, then the sections."""
+    import struct
+    import zlib
+    a = zlib.compress(stream.cpu().numpy().tobytes(), level)
+    b = zlib.compress(lossless_val.cpu().numpy().tobytes(), level)
+    return struct.pack("<QQQQ", stream.numel(), lossless_val.numel(), len(a), len(b)) + a + b
+
+
+def decompress_edits(blob: bytes, device="cuda") -> Tuple[torch.Tensor, torch.Tensor]:
+    import struct
+    import zlib
+
+    import numpy as np
+    nw, nl, la, lb = struct.unpack_from("<QQQQ", blob, 0)
+    a = zlib.decompress(blob[32:32 + la])
+    b = zlib.decompress(blob[32 + la:32 + la + lb])
+    stream = torch.from_numpy(np.frombuffer(a, dtype=np.int32).copy()).to(device)
+    val = torch.from_numpy(np.frombuffer(b, dtype=np.float32).copy()).to(device)
+    if stream.numel() != nw or val.numel() != nl:
+        raise ValueError("corrupt edit record")
+    return stream, val
 
 
 def dmt_correct_noalloc(ctx: Context, f: torch.Tensor, g_hat: torch.Tensor, xi: float, g_out: torch.Tensor,
@@ -477,8 +582,9 @@ class Server:
         self._held[t.value] = (f, g_hat, g_out, q_out)
         return t.value
 
-    def poll(self, ticket: int, wait: bool = False) -> Optional[Result]:
-        """Result of a finished ticket (then released), or None while it runs."""
+    def poll(self, ticket: int, wait: bool = False, lossless: bool = True) -> Optional[Result]:
+        """Result of a finished ticket (then released), or None while it runs.  With lossless, the
+        library also reads the job's lossless edits from its outputs."""
         j = dmt_job()
         st = self.L.dmt_server_poll(self.h, ticket, 1 if wait else 0, C.byref(j))
         if st == DMT_W_PENDING:
@@ -488,7 +594,7 @@ class Server:
         f, gh, g_out, q_out = self._held.pop(ticket)
         stj = int(j.status)
         idx = val = None
-        if stj >= 0:
+        if stj >= 0 and lossless:
             if self._ctx is None:
                 self._ctx = Context(g_out.device.index or 0)
             idx, val = dmt_lossless_list(self._ctx, q_out, g_out)

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _declared():
     src = open(os.path.join(ROOT, "include", "dmt.h")).read()
-    return sorted(set(re.findall(r"^\s*(?:dmt_status|const char \*|int64_t)\s*(dmt_\w+)\s*\(", src, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:dmt_status|const char \*|int64_t|int32_t)\s*(dmt_\w+)\s*\(", src, re.M)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -54,3 +54,10 @@ def test_noalloc_scratch_size_matches_header():
     src = open(os.path.join(ROOT, "include", "dmt.h")).read()
     m = re.search(r"#define DMT_NOALLOC_SCRATCH_BYTES (\d+)LL", src)
     assert m and int(m.group(1)) == dmt.DMT_NOALLOC_SCRATCH_BYTES
+
+
+def test_edit_bits():
+    from paper_2409_17346_amd import dmt
+    L = dmt.load_library()
+    assert [L.dmt_edit_bits(q) for q in range(8)] == [1, 2, 2, 3, 3, 3, 3, 4]
+    assert L.dmt_edit_bits(-1) == -1 and L.dmt_edit_bits(8) == -1

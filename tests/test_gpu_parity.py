@@ -467,3 +467,93 @@ def test_lossless_list_matches_correct(ctx, dmt):
     idx, val = dmt.dmt_lossless_list(ctx, r.q, r.g)
     assert r.lossless_idx.numel() > 0
     assert torch.equal(idx, r.lossless_idx) and torch.equal(val.view(torch.int32), r.lossless_val.view(torch.int32))
+
+
+AGREE_CASES = [((12, 9), "uniform", 0.2), ((64, 48), "smooth", 0.01), ((130, 67), "plateau", 0.05),
+               ((5, 4, 3), "uniform", 0.2), ((12, 10, 9), "smooth", 0.02), ((20, 17, 19), "plateau", 0.05)]
+
+
+@pytest.mark.parametrize("shape,kind,rel", AGREE_CASES)
+def test_compare_msc(ctx, dmt, shape, kind, rel):
+    """Critical-cell and separatrix agreement counts (the recall / precision of Section 5.1) equal
+    the oracle's, for g_hat and for the fields corrected at tiers 2 and 4."""
+    w = synth.tiny_cases(7, shape, rel=rel, kind=kind, ghat="noise")
+    cx = oracle.Complex.grid(*w.dims)
+    f = w.f.reshape(-1)
+    for tier in (0, 2, 4):
+        status = "ok"
+        if tier == 0:
+            g = w.g_hat
+        else:
+            r = dmt.dmt_correct(ctx, _t(w.f), _t(w.g_hat), w.xi, tier, 6)
+            g, status = r.g.cpu().numpy(), r.status
+        a = dmt.dmt_compare_msc(ctx, _t(w.f), _t(g))
+        o = oracle.msc_agreement(cx, f, g.reshape(-1))
+        for k, v in o.items():
+            assert a[k] == v, (tier, k)
+        if tier == 4 and status == "ok":
+            assert a["critical_recall"] == a["critical_precision"] == 1.0
+            assert a["separatrix_recall"] == 1.0
+
+
+def test_compare_msc_small2d_config(ctx, dmt):
+    w = synth.config_small2d()
+    r = dmt.dmt_correct(ctx, _t(w.f), _t(w.g_hat), w.xi, 4, 6)
+    cx = oracle.Complex.grid(*w.dims)
+    for g in (w.g_hat, r.g.cpu().numpy()):
+        a = dmt.dmt_compare_msc(ctx, _t(w.f), _t(g))
+        o = oracle.msc_agreement(cx, w.f.reshape(-1), g.reshape(-1))
+        for k, v in o.items():
+            assert a[k] == v, k
+    assert a["separatrix_recall"] == a["separatrix_precision"] == a["critical_recall"] == 1.0
+
+
+@pytest.mark.parametrize("q_max", range(8))
+def test_edit_stream_random(ctx, dmt, q_max):
+    """The packed stream equals the oracle's bit for bit (codes straddling words, ragged tails);
+    the decoder returns the counts."""
+    rng = np.random.default_rng(100 + q_max)
+    for n in (1, 33, 4099, 70001):
+        q = rng.integers(0, q_max + 2, size=n).astype(np.uint8)
+        q[q == q_max + 1] = 0xFF
+        g = rng.uniform(0, 1, size=n).astype(np.float32)
+        stream, val = dmt.dmt_pack_edits(ctx, _t(q, torch.uint8), _t(g), q_max)
+        assert np.array_equal(stream.cpu().numpy().view(np.uint32), oracle.pack_edits(q, q_max))
+        assert np.array_equal(val.cpu().numpy().view(np.uint32), g[q == 0xFF].view(np.uint32))
+        gh = rng.uniform(0, 1, size=n).astype(np.float32)
+        xi = 0.01
+        g2, q2 = dmt.dmt_unpack_edits(ctx, stream, val, _t(gh), xi, q_max)
+        assert np.array_equal(q2.cpu().numpy(), q)
+        ref = oracle.decode(gh, q, np.nonzero(q == 0xFF)[0], g[q == 0xFF], xi, q_max)
+        assert np.array_equal(g2.cpu().numpy().view(np.uint32), ref.view(np.uint32))
+
+
+@pytest.mark.parametrize("case", ["small2d", "tiny3d"])
+def test_edit_stream_of_a_correction(ctx, dmt, case):
+    """dmt_correct -> stream + lossless values -> DEFLATE -> inflate -> decoder gives g' bit for bit."""
+    w = synth.config_small2d() if case == "small2d" else synth.tiny_cases(13, (12, 10, 9), rel=0.05, kind="smooth",
+                                                                          ghat="noise")
+    r = dmt.dmt_correct(ctx, _t(w.f), _t(w.g_hat), w.xi, 4, w.q_max)
+    stream, val = dmt.dmt_pack_edits(ctx, r.q, r.g, w.q_max)
+    assert val.numel() == r.stats["n_lossless"]
+    assert torch.equal(val.view(torch.int32), r.lossless_val.view(torch.int32))
+    blob = dmt.compress_edits(stream, val)
+    s2, v2 = dmt.decompress_edits(blob)
+    g2, q2 = dmt.dmt_unpack_edits(ctx, s2, v2, _t(w.g_hat), w.xi, w.q_max)
+    assert torch.equal(g2.view(torch.int32), r.g.view(torch.int32)) and torch.equal(q2, r.q)
+
+
+def test_edit_stream_errors(ctx, dmt):
+    q = torch.zeros(100, dtype=torch.uint8, device="cuda")
+    g = torch.zeros(100, device="cuda")
+    q[5] = 9                                   # above q_max = 6 and not the lossless marker
+    with pytest.raises(dmt.DmtError):
+        dmt.dmt_pack_edits(ctx, q, g, 6)
+    q[5] = 0xFF
+    stream, val = dmt.dmt_pack_edits(ctx, q, g, 6)
+    with pytest.raises(dmt.DmtError):         # one lossless vertex marked, none given
+        dmt.dmt_unpack_edits(ctx, stream, val[:0], g, 0.1, 6)
+    bad = torch.full(((100 * 4 + 31) // 32,), -1, dtype=torch.int32, device="cuda")
+    with pytest.raises(dmt.DmtError) as e:     # every 4-bit code of q_max 7 reads 15 > 8
+        dmt.dmt_unpack_edits(ctx, bad, val, g, 0.1, 7)
+    assert "code above" in str(e.value)

@@ -575,3 +575,119 @@ def test_floor_collision_check_rejects_other_stalls():
     assert len(res) > 0
     lo, _ = oracle.bounds(f, 100.0)
     assert not explained((nx, ny, 1), f, gh, lo, res).any()
+
+
+# ------------------------------------------------------------------------------------------
+# Verification metrics (Section 5.1): agreement of two complexes
+
+def _brute_agreement(cells, f, g):
+    """Agreement counts from two brute-force complexes (cells as vertex sets, separatrices keyed
+    by their saddle and first cell)."""
+    bf, bg = brute.msc(cells, f), brute.msc(cells, g)
+    n = len(cells) - 1
+    out = {"crit_f": [0] * 4, "crit_g": [0] * 4, "crit_common": [0] * 4}
+    for d in range(n + 1):
+        a, b = set(bf["crit"][d]), set(bg["crit"][d])
+        out["crit_f"][d], out["crit_g"][d], out["crit_common"][d] = len(a), len(b), len(a & b)
+
+    def desc(m):
+        return {(e, p[0]): (p[-1], p) for e, p in m["desc"]}
+
+    def asc(m):
+        return {(s, p[0]): (t, p) for s, p, t in m["asc"]}
+
+    out.update(sep_f=[0, 0], sep_g=[0, 0], sep_same_ends=[0, 0], sep_same_cells=[0, 0])
+    for k, fam in enumerate((desc, asc)):
+        sf, sg = fam(bf), fam(bg)
+        out["sep_f"][k], out["sep_g"][k] = len(sf), len(sg)
+        for key, (t, p) in sf.items():
+            if key in sg:
+                out["sep_same_ends"][k] += sg[key][0] == t
+                out["sep_same_cells"][k] += sg[key] == (t, p)
+    return out
+
+
+@pytest.mark.parametrize("shape", [(5, 4), (7, 6), (3, 3, 3), (4, 3, 3)])
+def test_agreement_matches_brute_force(shape):
+    """The oracle's agreement counts equal those of two brute-force complexes, for g_hat (which
+    changes the complex) and for corrections at tiers 1-3 (which restore parts of it)."""
+    nx, ny = shape[0], shape[1]
+    nz = shape[2] if len(shape) == 3 else 1
+    cx = oracle.Complex.grid(nx, ny, nz)
+    cells = brute.kuhn_complex(shape)
+    seen_partial = False
+    for seed in range(5):
+        w = synth.tiny_cases(seed, (nz, ny, nx) if nz > 1 else (ny, nx), rel=0.2, kind="uniform", ghat="noise")
+        f, gh = w.f.reshape(-1), w.g_hat.reshape(-1)
+        gs = [gh] + [oracle.correct(cx, f, gh, w.xi, t, 6)["g"] for t in (1, 2, 3)]
+        for g in gs:
+            a = oracle.msc_agreement(cx, f, g)
+            assert a == _brute_agreement(cells, f, g)
+            seen_partial |= sum(a["crit_common"]) < sum(a["crit_f"])
+    assert seen_partial
+
+
+@pytest.mark.parametrize("dims", [(12, 9, 1), (6, 5, 4)])
+def test_agreement_invariants(dims):
+    """The complex depends only on the order of the values: any increasing transform of f agrees
+    with f in full; the counts are symmetric in f and g; a field corrected at tier t agrees with f
+    in critical cells (t >= 2), separatrix ends (t >= 3) and separatrix cells (t = 4)."""
+    nx, ny, nz = dims
+    cx = oracle.Complex.grid(nx, ny, nz)
+    shape = (nz, ny, nx) if nz > 1 else (ny, nx)
+    for seed in range(4):
+        w = synth.tiny_cases(seed, shape, rel=0.05, kind="smooth", ghat="noise")
+        f, gh = w.f.reshape(-1).astype(np.float64), w.g_hat.reshape(-1)
+        for g in (f + 3.0, 2.0 * f - 1.0, np.cbrt(f + 0.25)):
+            a = oracle.msc_agreement(cx, f, g.astype(np.float32))
+            assert a["crit_common"] == a["crit_f"] == a["crit_g"]
+            assert a["sep_same_cells"] == a["sep_same_ends"] == a["sep_f"] == a["sep_g"]
+        a, b = oracle.msc_agreement(cx, f, gh), oracle.msc_agreement(cx, gh, f)
+        assert a["crit_common"] == b["crit_common"] and a["crit_f"] == b["crit_g"]
+        assert a["sep_same_cells"] == b["sep_same_cells"] and a["sep_same_ends"] == b["sep_same_ends"]
+        for tier in (2, 3, 4):
+            o = oracle.correct(cx, f, gh, w.xi, tier, 6)
+            if o["status"] != "ok":
+                continue
+            a = oracle.msc_agreement(cx, f, o["g"])
+            assert a["crit_common"] == a["crit_f"] == a["crit_g"]
+            if tier >= 3:
+                assert a["sep_same_ends"] == a["sep_f"] == a["sep_g"]
+            if tier == 4:
+                assert a["sep_same_cells"] == a["sep_f"]
+
+
+# ------------------------------------------------------------------------------------------
+# Edit stream (Section 4.7): fixed-bit codes, lossless values in vertex order
+
+def test_edit_stream_hand_examples():
+    assert [oracle.edit_bits(q) for q in range(8)] == [1, 2, 2, 3, 3, 3, 3, 4]
+    # q_max 6: 3-bit codes, the 11th code (lossless = 7) straddles the first word boundary:
+    # 1 + 2*8 + 7*64 + 5*4096 + 6*32768 + 3*262144 + (7 << 30 mod 2^32) = 3222229457, then bit 32 = 1
+    assert oracle.pack_edits([1, 2, 0xFF, 0, 5, 6, 3, 0, 0, 0, 0xFF], 6).tolist() == [3222229457, 1]
+    # q_max 0: 1-bit codes, alternating 0 / lossless
+    assert oracle.pack_edits([0, 0xFF] * 18, 0).tolist() == [0xAAAAAAAA, 0b1010]
+    # q_max 7: 4-bit codes, lossless = 8
+    assert oracle.pack_edits([7, 0xFF, 1], 7).tolist() == [7 | 8 << 4 | 1 << 8]
+
+
+@pytest.mark.parametrize("q_max", range(8))
+def test_edit_stream_round_trip(q_max):
+    rng = np.random.default_rng(q_max)
+    for n in (1, 31, 32, 33, 1000, 4099):
+        q = rng.integers(0, q_max + 2, size=n).astype(np.uint8)
+        q[q == q_max + 1] = 0xFF
+        words = oracle.pack_edits(q, q_max)
+        assert len(words) == (n * oracle.edit_bits(q_max) + 31) // 32
+        assert np.array_equal(oracle.unpack_edits(words, n, q_max), q)
+
+
+def test_edit_stream_decodes_a_correction():
+    """Stream + lossless values in vertex order reproduce the corrected field bit for bit."""
+    w = synth.config_small2d()
+    cx = oracle.Complex.grid(*w.dims)
+    o = oracle.correct(cx, w.f.reshape(-1), w.g_hat.reshape(-1), w.xi, 4, 6)
+    q = oracle.unpack_edits(oracle.pack_edits(o["q"], 6), len(o["q"]), 6)
+    idx = np.nonzero(q == 0xFF)[0]
+    g = oracle.decode(w.g_hat.reshape(-1), q, idx, o["g"][idx], w.xi, 6)
+    assert np.array_equal(g.view(np.uint32), o["g"].view(np.uint32))
