@@ -319,12 +319,102 @@ def bench_served(args):
     ctx.close()
 
 
+def _edit_sizes(ctx, dmt, torch, r, w, q_max: int) -> dict:
+    """Storage of a correction's edits (Section 4.7, Table 5): the fixed-bit stream plus lossless
+    values after DEFLATE (standing in for ZSTD), beside the same edits as floating key-value pairs
+    (vertex index int32, delta = g' - g_hat fp32, DEFLATE), and, for 2*xi-bin g_hat, the overall
+    compression ratio with the bin indices under DEFLATE as the base compressor's output."""
+    import zlib
+
+    import numpy as np
+    stream, val = dmt.dmt_pack_edits(ctx, r.q, r.g, q_max)
+    blob = dmt.compress_edits(stream, val)
+    q = r.q.cpu().numpy().reshape(-1)
+    idx = np.nonzero(q)[0]
+    delta = (r.g.cpu().numpy().reshape(-1)[idx].astype(np.float64) - w.g_hat.reshape(-1)[idx]).astype(np.float32)
+    floating = zlib.compress(idx.astype(np.int32).tobytes() + delta.tobytes(), 9)
+    out = {"edit_bytes": len(blob), "stream_bits": int(stream.numel() * 32), "lossless_values": int(val.numel()),
+           "floating_edit_bytes": len(floating), "edit_ratio": round(len(idx) / q.size, 6)}
+    if w.meta.get("ghat") == "bin":
+        codes = np.rint(w.f.astype(np.float64) / (2.0 * w.xi)).astype(np.int32)
+        base = len(zlib.compress(codes.tobytes(), 9))
+        raw = 4 * q.size
+        out.update(base_bytes=base, cr=round(raw / base, 3), ocr=round(raw / (base + len(blob)), 3),
+                   ocr_floating=round(raw / (base + len(floating)), 3))
+    return out
+
+
+def _timed_correct(ctx, dmt, torch, w, tier: int, q_max: int, reps: int = 3):
+    f = torch.from_numpy(w.f).cuda()
+    gh = torch.from_numpy(w.g_hat).cuda()
+    best, r = float("inf"), None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = dmt.dmt_correct(ctx, f, gh, w.xi, tier, q_max)
+        torch.cuda.synchronize()
+        best = min(best, time.perf_counter() - t0)
+    return best, r, f
+
+
+def bench_sweep(args):
+    """Sweeps on synthetic stand-ins of the paper's studies (one JSON line, entries under "sweep"):
+    qmax    - Section 5.5 / Figure 10: q_max 2..7 at relative bounds 1e-5..1e-2 on a 150 x 450 2D
+              field (Heated Flow's shape): time, iterations, edit storage and OCR;
+    tiers   - Section 5.3 / Figure 11: tiers 1-4 at relative bounds 1e-4..1e-2 on a 361 x 576 2D
+              field (IVT's shape): time, iterations, edit storage, and the MSC agreement
+              (critical / separatrix recall and precision, Section 5.1) each tier reaches;
+    extreme - Section 5.9 / Figure 14: i.i.d. noise in [0, xi) with the absolute bound xi = 1e-4, so
+              g_hat is flat, at sides 64..2048: time, iterations and how much of the field is edited."""
+    import numpy as np
+    import torch
+    from paper_2409_17346_amd import dmt, synth
+    ctx = dmt.Context(0)
+    rows, total_bytes, total_s = [], 0.0, 0.0
+    kind = args.workload.split("-", 1)[1]
+    if kind == "qmax":
+        cases = [(synth.flow2d(150, 450, 3, rel), 4, qm) for rel in (1e-5, 1e-4, 1e-3, 1e-2) for qm in range(2, 8)]
+    elif kind == "tiers":
+        cases = [(synth.flow2d(361, 576, 4, rel), t, 6) for rel in (1e-4, 1e-3, 1e-2) for t in (1, 2, 3, 4)]
+    else:
+        cases = [(synth.extreme_noise2d(side, 1), 4, 6) for side in (64, 128, 256, 512, 1024, 2048)]
+    for w, tier, q_max in cases:
+        sec, r, f = _timed_correct(ctx, dmt, torch, w, tier, q_max)
+        row = {"field": w.name, "tier": tier, "q_max": q_max, "ms": round(sec * 1e3, 3),
+               "mb_per_s": round(4.0 * w.f.size / sec / 1e6, 3), "status": r.status,
+               "iterations": r.stats["iterations"], "c_iterations": r.stats["c_iterations"],
+               "s_iterations": r.stats["s_iterations"], "n_edited": r.stats["n_edited"],
+               "n_lossless": r.stats["n_lossless"]}
+        row.update(_edit_sizes(ctx, dmt, torch, r, w, q_max))
+        if kind == "tiers":
+            a = dmt.dmt_compare_msc(ctx, f, r.g)
+            row.update({k: round(v, 6) for k, v in a.items() if isinstance(v, float)})
+        if kind == "extreme":
+            q = r.q.cpu().numpy()
+            row["fraction_at_q_max"] = round(float((q == q_max).mean()), 6)
+            row["fraction_edited"] = round(float((q != 0).mean()), 6)
+        rows.append(row)
+        total_bytes += 4.0 * w.f.size
+        total_s += sec
+        print(f"[bench] {json.dumps(row)}", file=sys.stderr, flush=True)
+    line = {
+        "metric": METRIC, "value": round(total_bytes / total_s / 1e6, 3), "unit": "MB/s", "n_gpus": 1,
+        "steps": len(rows), "warmup": 0, "ms_per_step": round(total_s / len(rows) * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": args.workload, "runs": len(rows), "timing": "best of 3 per run"},
+        "sweep": rows,
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="large2d", choices=["large2d", "small2d", "atoms3d", "batch64", "served"])
+    ap.add_argument("--workload", default="large2d", choices=["large2d", "small2d", "atoms3d", "batch64", "served", "sweep-qmax",
+                             "sweep-tiers", "sweep-extreme"])
     ap.add_argument("--requests", type=int, default=200, help="served: requests in the stream")
     ap.add_argument("--cpu-sample-iters", type=int, default=40,
                     help="iterations of the oracle timed on the full input for the CPU baseline")
@@ -351,6 +441,8 @@ def main():
         return bench_batch(args)
     if args.workload == "served":
         return bench_served(args)
+    if args.workload.startswith("sweep-"):
+        return bench_sweep(args)
     if args.copy_probe_mib > 0:
         src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

@@ -338,6 +338,31 @@ def served_job(j: int, big_side: int = 384) -> Workload:
 # ---------------------------------------------------------------------------------------------
 # Small random cases for tests
 
+def flow2d(ny: int, nx: int, seed: int, rel: float = 1e-4, ghat: str = "bin") -> Workload:
+    """2D ny x nx field from the 2048^2 generator (Gaussians of width ~ side/128 * U[3,12] plus
+    4-octave value noise) on a square of side max(ny, nx), cropped; the stand-in for the paper's
+    2D climate and flow fields in the q_max sweep (150 x 450, Heated Flow's shape) and the tier
+    study (361 x 576, IVT's shape).  g_hat = 2*xi bins or f + U[-xi, xi]."""
+    rng = np.random.default_rng([seed, ny, nx])
+    side = max(ny, nx)
+    f = gauss2d_value_noise(side, max(4, int(round(256 * side * side / 2048 ** 2))), seed, rng=rng)
+    f = _normalize01(f[:ny, :nx].astype(np.float64)).astype(np.float32)
+    xi = xi_from_relative(f, rel)
+    g = bin_quantize(f, xi) if ghat == "bin" else uniform_noise(f, xi, rng)
+    return Workload(f"2d-{ny}x{nx}-flow-{ghat}-{rel:g}", f, g, xi, 4, 6, {"rel": rel, "ghat": ghat, "seed": seed})
+
+
+def extreme_noise2d(side: int, seed: int, xi: float = 1e-4) -> Workload:
+    """The paper's extreme case (Section 5.9): i.i.d. noise f ~ U[0, xi) with the absolute bound xi,
+    so the 2*xi-bin quantizer returns an exactly flat g_hat = 0 and destroys every local order."""
+    rng = np.random.default_rng([seed, side])
+    xi32 = float(np.float32(xi))
+    f = (rng.uniform(0.0, xi32, size=(side, side))).astype(np.float32)
+    f = np.minimum(f, np.nextafter(np.float32(xi32), np.float32(0)))
+    return Workload(f"2d-{side}-noise-flat-xi{xi:g}", f, bin_quantize(f, xi32), xi32, 4, 6,
+                    {"abs": xi32, "ghat": "bin", "seed": seed})
+
+
 def random_field(shape, kind: str, seed: int) -> np.ndarray:
     """Small test fields: 'uniform' U[0,1), 'plateau' (few distinct values, many ties),
     'perm' (a random permutation of 0..N-1), 'const' (all equal), 'smooth' (few Gaussians)."""

@@ -557,3 +557,32 @@ def test_edit_stream_errors(ctx, dmt):
     with pytest.raises(dmt.DmtError) as e:     # every 4-bit code of q_max 7 reads 15 > 8
         dmt.dmt_unpack_edits(ctx, bad, val, g, 0.1, 7)
     assert "code above" in str(e.value)
+
+
+@pytest.mark.parametrize("side", [64, 100, 128])
+def test_extreme_flat_noise(ctx, dmt, side):
+    """The extreme case (noise in [0, xi), flat g_hat): oracle's results bit for bit."""
+    r, o = _compare_correction(ctx, dmt, synth.extreme_noise2d(side, 1))
+    assert r.status == "ok" and r.stats["n_edited"] > side * side // 3
+
+
+@pytest.mark.parametrize("q_max", range(2, 8))
+@pytest.mark.parametrize("rel", [1e-4, 1e-3])
+def test_qmax_sweep_field(ctx, dmt, q_max, rel):
+    """The q_max sweep's 150 x 450 field: oracle's results for every q_max."""
+    _compare_correction(ctx, dmt, synth.flow2d(150, 450, 3, rel), q_max=q_max)
+
+
+@pytest.mark.parametrize("tier", [1, 2, 3, 4])
+def test_tier_study_field(ctx, dmt, tier):
+    """The tier study's 361 x 576 field: oracle's results at every tier, and the agreement each
+    tier guarantees."""
+    w = synth.flow2d(361, 576, 4, 1e-4)
+    r, o = _compare_correction(ctx, dmt, w, tier=tier)
+    a = dmt.dmt_compare_msc(ctx, _t(w.f), r.g)
+    if tier >= 2:
+        assert a["critical_recall"] == a["critical_precision"] == 1.0
+    if tier >= 3:
+        assert a["separatrix_recall_connectivity"] == 1.0
+    if tier == 4:
+        assert a["separatrix_recall"] == a["separatrix_precision"] == 1.0
