@@ -75,16 +75,24 @@ typedef struct {
     int32_t tier;              /* dmt_tier */
     int32_t q_max;             /* 0..7: edit step xi / 2^q_max (Equation 2); the paper uses 6 */
     int64_t max_iters;         /* cap on edit iterations (C + S); < 0 means no cap */
-    uint32_t flags;            /* 0, or DMT_F_DENSE / DMT_F_PHASES */
+    uint32_t flags;            /* 0, or DMT_F_DENSE / DMT_F_PHASES, and DMT_F_SADDLE_SADDLE */
 } dmt_options;
 
-/* Option flags (results are bit-identical in every form; they exist for testing):
+/* Option flags.  The first two choose how the loop runs (results are bit-identical in every
+ * form; they exist for testing):
  * DMT_F_DENSE   recompute the whole gradient and every violation each iteration instead of only
  *               around the vertices edited in the previous iteration;
  * DMT_F_PHASES  run every iteration as full-grid kernel launches, one per phase, instead of
- *               inside one workgroup that stays resident for the whole loop. */
+ *               inside one workgroup that stays resident for the whole loop.
+ * DMT_F_SADDLE_SADDLE  (3D, tier 4) also preserve the saddle-saddle connectors (Section 3.1;
+ *               Section 4.4, 1-dimensional troublemakers): the separatrix step walks f's 1-2 V-paths
+ *               down from every 2-saddle through edges paired alike in f and g, and an edge paired
+ *               differently in g is a troublemaker (edge ij paired with ijk in f: lower k).  Every
+ *               edge these walks reach then pairs as in f, so g's connectors equal f's.  No effect
+ *               in 2D or below tier 4. */
 #define DMT_F_DENSE 1u
 #define DMT_F_PHASES 2u
+#define DMT_F_SADDLE_SADDLE 4u
 
 typedef struct {
     int64_t iterations;        /* edit iterations applied (C + S) */
@@ -104,9 +112,10 @@ typedef struct {
  * the work of the frontier forms in that iteration (0 in the dense form): dirty vertices,
  * affected anchors, listed violating anchors, branches whose first differing cell was
  * settled, branch cells examined while settling them, branch cells touched (on dirty vertices
- * whose own or top-cell pairing changed), and the duration
- * of the iteration in the resident loop in 10 ns ticks (0 elsewhere; timing, not a result). */
-#define DMT_LOG_WORDS 20
+ * whose own or top-cell pairing changed), the duration
+ * of the iteration in the resident loop in 10 ns ticks (0 elsewhere; timing, not a result), and
+ * TM_ss (saddle-saddle troublemaker edges, DMT_F_SADDLE_SADDLE). */
+#define DMT_LOG_WORDS 21
 
 /* ---- context ----------------------------------------------------------------------------- */
 

@@ -65,11 +65,11 @@ def lib():
     L.omsc_free.argtypes = [C.c_void_p]
     L.oracle_bounds.argtypes = [PF, C.c_int64, C.c_float, PF, PF]
     L.oracle_correct.restype = C.c_int
-    L.oracle_correct.argtypes = [C.c_void_p, PF, PF, C.c_float, C.c_int, C.c_int, C.c_int64,
+    L.oracle_correct.argtypes = [C.c_void_p, PF, PF, C.c_float, C.c_int, C.c_int, C.c_int, C.c_int64,
                                  PF, P8, P64, P64, C.c_int64]
     L.oracle_decode.argtypes = [PF, P8, C.c_int64, P64, PF, C.c_int64, C.c_float, C.c_int, PF]
     L.oracle_residual.restype = C.c_int64
-    L.oracle_residual.argtypes = [C.c_void_p, PF, PF, C.c_int, P64, P64, C.c_int64]
+    L.oracle_residual.argtypes = [C.c_void_p, PF, PF, C.c_int, C.c_int, P64, P64, C.c_int64]
     _lib = L
     return L
 
@@ -250,14 +250,17 @@ LOG_KEYS = ["kind", "FP0", "FN0", "FP1", "FN1", "FP2", "FN2", "FP3", "FN3", "TM_
 
 
 def correct(cx: Complex, f, g_hat, xi: float, tier: int = 4, q_max: int = 6, max_iters: int = 1 << 40,
-            log_cap: int = 100000) -> dict:
+            log_cap: int = 100000, saddle_saddle: bool = False) -> dict:
+    """The correction (Sections 4.3-4.5); saddle_saddle adds the saddle-saddle connectors of a 3D
+    complex to the separatrix step at tier 4 (log word 13 counts their troublemakers)."""
     f = _f32(f)
     g_hat = _f32(g_hat)
     g = np.zeros_like(f)
     q = np.zeros(f.size, dtype=np.uint8)
     stats = np.zeros(10, dtype=np.int64)
     log = np.zeros((max(log_cap, 1), 16), dtype=np.int64)
-    rc = lib().oracle_correct(cx.h, _p(f, PF), _p(g_hat, PF), C.c_float(xi), tier, q_max, max_iters,
+    rc = lib().oracle_correct(cx.h, _p(f, PF), _p(g_hat, PF), C.c_float(xi), tier, int(saddle_saddle), q_max,
+                              max_iters,
                               _p(g, PF), _p(q, P8), _p(stats, P64), _p(log, P64), log_cap)
     st = dict(zip(STAT_KEYS, (int(x) for x in stats)))
     out = {"status": STATUS[rc], "stats": st}
@@ -268,7 +271,7 @@ def correct(cx: Complex, f, g_hat, xi: float, tier: int = 4, q_max: int = 6, max
     return out
 
 
-def residual(cx: Complex, f, g, tier: int = 4):
+def residual(cx: Complex, f, g, tier: int = 4, saddle_saddle: bool = False):
     """Violations of g against f (what the correction loop would fix next): an int64 array of
     (dimension, cell id) rows -- cells whose criticality differs, else at tier >= 3 the first
     differing cell of each checked separatrix branch."""
@@ -276,10 +279,11 @@ def residual(cx: Complex, f, g, tier: int = 4):
     g = _f32(g)
     L = lib()
     z = np.zeros(1, dtype=np.int64)
-    n = L.oracle_residual(cx.h, _p(f, PF), _p(g, PF), tier, _p(z, P64), _p(z, P64), 0)
+    ss = int(saddle_saddle)
+    n = L.oracle_residual(cx.h, _p(f, PF), _p(g, PF), tier, ss, _p(z, P64), _p(z, P64), 0)
     dims = np.zeros(max(n, 1), dtype=np.int64)
     ids = np.zeros(max(n, 1), dtype=np.int64)
-    L.oracle_residual(cx.h, _p(f, PF), _p(g, PF), tier, _p(dims, P64), _p(ids, P64), n)
+    L.oracle_residual(cx.h, _p(f, PF), _p(g, PF), tier, ss, _p(dims, P64), _p(ids, P64), n)
     return np.stack([dims[:n], ids[:n]], axis=1)
 
 

@@ -135,3 +135,55 @@ def msc(cells: List[List[Cell]], h, key=None):
             p, term = asc(T)
             aseps.add((s, p, term))
     return {"crit": crit, "desc": dseps, "asc": aseps, "pair": pair}
+
+
+def _edges_of(t: Cell) -> List[Cell]:
+    return [frozenset(p) for p in itertools.combinations(sorted(t), 2)]
+
+
+def connectors(cells: List[List[Cell]], h, key=None, cap: int = 200000):
+    """Saddle-saddle connectors of a 3D complex (Section 3.1): every V-path of the 1-2 level from a
+    critical triangle (2-saddle) down to a critical edge (1-saddle), enumerated by depth-first
+    search as (triangle, edge, triangle, ..., edge) tuples.  A path leaves the level at an edge
+    paired with a vertex."""
+    pair, crit, _ = gradient(cells, h, key)
+    out = set()
+
+    def walk(e, path):
+        if len(out) > cap:
+            raise RuntimeError("too many connector paths")
+        if e in crit[1]:
+            out.add(tuple(path + [e]))
+            return
+        t = pair.get(e)
+        if t is None or len(t) != 3:
+            return
+        for x in _edges_of(t):
+            if x != e:
+                walk(x, path + [e, t])
+
+    for t0 in crit[2]:
+        for e in _edges_of(t0):
+            walk(e, [t0])
+    return out
+
+
+def ss_troublemakers(cells: List[List[Cell]], f, g, key=None):
+    """Edges where g's 1-2 V-paths from the 2-saddles of f first leave f's: edges reachable from a
+    critical triangle of f through edges paired alike in f and g whose own pairing differs."""
+    pf, cf, _ = gradient(cells, f, key)
+    pg, _, _ = gradient(cells, g, key)
+    seen, out = set(), set()
+    stack = [e for t in cf[2] for e in _edges_of(t)]
+    while stack:
+        e = stack.pop()
+        if e in seen:
+            continue
+        seen.add(e)
+        if pf.get(e) != pg.get(e):
+            out.add(e)
+            continue
+        t = pf.get(e)
+        if t is not None and len(t) == 3:
+            stack.extend(x for x in _edges_of(t) if x != e)
+    return out

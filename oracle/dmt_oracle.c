@@ -605,6 +605,56 @@ static int64_t s_detect(state_t *st, const grad_t *F, const grad_t *G, const oms
     return total;
 }
 
+/* Saddle-saddle connectors (Section 3.1; Section 4.4, 1-dimensional troublemakers), in 3D.
+ * The V-paths of the 1-2 level of f descend from every critical triangle (2-saddle): from a
+ * triangle to each of its edges other than the one it is paired with, and from an edge paired
+ * with a triangle in f on to that triangle; a path ends at a critical edge (a 1-saddle, which
+ * makes it a saddle-saddle connector) or at an edge paired with a vertex.  These paths form a
+ * DAG from each 2-saddle.  Reading: tracing g's paths from the same 2-saddle follows f's as long
+ * as the edges met are paired alike; an edge whose pairing differs in g is where g's paths leave
+ * f's, the 1-dimensional troublemaker.  Its target is the apex of its f-pair (edge ij paired
+ * with triangle ijk in f but with ijl in g: lower k).  Edges beyond a troublemaker are not
+ * examined.  The troublemakers are the edges with a differing pairing that are reachable from a
+ * 2-saddle through edges paired alike, whatever order the DAG is walked in. */
+static void push_triangle_edges(const ocx *cx, int64_t t, int64_t skip, vec *stack) {
+    const int32_t *v = cx->verts[2] + t * 3;
+    const int32_t pairs[3][2] = {{v[0], v[1]}, {v[0], v[2]}, {v[1], v[2]}};
+    for (int k = 0; k < 3; k++) {
+        int64_t e = lookup(cx, 1, pairs[k]);
+        if (e >= 0 && e != skip) vpush(stack, e);
+    }
+}
+
+static int64_t ss_detect(state_t *st, const grad_t *F, const grad_t *G, int64_t *tm_ss, vec *where) {
+    const ocx *cx = st->cx;
+    if (cx->top != 3) return 0;
+    uint8_t *seen = xcalloc((size_t)cx->ncell[1], 1);
+    vec stack = {0};
+    for (int64_t t = 0; t < cx->ncell[2]; t++)
+        if (is_crit(cx, F, 2, t)) push_triangle_edges(cx, t, -1, &stack);
+    int64_t total = 0;
+    while (stack.n > 0) {
+        int64_t e = stack.p[--stack.n];
+        if (seen[e]) continue;
+        seen[e] = 1;
+        if (G->up[1][e] != F->up[1][e] || G->down[1][e] != F->down[1][e]) {
+            int lo_d; int64_t lo_id;
+            int32_t target = pair_apex(cx, F, 1, e, &lo_d, &lo_id);
+            if (target >= 0) {
+                st->req[target] = 1;
+                if (where) { vpush(where, 1); vpush(where, e); }
+                (*tm_ss)++;
+                total++;
+            }
+            continue;
+        }
+        if (F->up[1][e] >= 0) push_triangle_edges(cx, F->up[1][e], e, &stack);
+    }
+    free(stack.p);
+    free(seen);
+    return total;
+}
+
 /* Equation 2, once for every requested vertex (Jacobi: all requests of an iteration are
  * collected on g^(k) first, then each requested vertex takes exactly one step).
  * Reading: g = g_hat - q*Delta is formed from g_hat in one rounding (not by repeated
@@ -634,7 +684,7 @@ static int64_t apply_requests(state_t *st, int64_t *n_req) {
 
 static uint32_t fbits(float x) { uint32_t u; memcpy(&u, &x, 4); return u; }
 
-int oracle_correct(const ocx *cx, const float *f, const float *g_hat, float xi, int tier,
+int oracle_correct(const ocx *cx, const float *f, const float *g_hat, float xi, int tier, int ss,
                    int q_max, int64_t max_iters, float *g_out, uint8_t *q_out, int64_t *stats,
                    int64_t *log, int64_t log_cap) {
     memset(stats, 0, sizeof(int64_t) * 10);
@@ -679,6 +729,7 @@ int oracle_correct(const ocx *cx, const float *f, const float *g_hat, float xi, 
         int kind = 1;
         if (viol == 0 && tier >= 3) {
             viol = s_detect(&st, &F, &G, mf, tier, rec + 9, rec + 10, NULL);
+            if (tier == 4 && ss) viol += ss_detect(&st, &F, &G, rec + 13, NULL);
             kind = 2;
         }
         if (viol == 0) { converged = 1; break; }
@@ -720,8 +771,8 @@ int oracle_correct(const ocx *cx, const float *f, const float *g_hat, float xi, 
  * whose criticality differs (Section 4.3), or, when there are none and tier >= 3, the first
  * differing cell of every separatrix branch that the tier checks (Section 4.4), one entry per
  * branch.  Writes up to cap (dimension, cell id) pairs; returns the total count. */
-int64_t oracle_residual(const ocx *cx, const float *f, const float *g, int tier, int64_t *dims, int64_t *ids,
-                        int64_t cap) {
+int64_t oracle_residual(const ocx *cx, const float *f, const float *g, int tier, int ss, int64_t *dims,
+                        int64_t *ids, int64_t cap) {
     int64_t nv = cx->nv;
     state_t st = {0};
     st.cx = cx; st.f = f; st.ghat = g; st.g = (float *)g;
@@ -737,6 +788,7 @@ int64_t oracle_residual(const ocx *cx, const float *f, const float *g, int tier,
     if (viol == 0 && tier >= 3) {
         omsc *mf = msc_from_grad(cx, &F);
         viol = s_detect(&st, &F, &G, mf, tier, cnt + 9, cnt + 10, &where);
+        if (tier == 4 && ss) viol += ss_detect(&st, &F, &G, cnt + 13, &where);
         omsc_free(mf);
     }
     for (int64_t k = 0; k < viol && k < cap; k++) { dims[k] = where.p[2 * k]; ids[k] = where.p[2 * k + 1]; }

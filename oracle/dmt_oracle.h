@@ -61,21 +61,23 @@ void omsc_free(omsc *m);
 /* Smallest fp32 >= f[i] - xi and largest fp32 <= f[i] + xi, in exact arithmetic. */
 void oracle_bounds(const float *f, int64_t n, float xi, float *lo, float *hi);
 
-/* Full correction.  stats[0..9] = iterations, c_iterations, s_iterations, n_edited,
+/* Full correction.  ss != 0 adds the saddle-saddle connectors of a 3D complex to the separatrix
+ * step at tier 4.  stats[0..9] = iterations, c_iterations, s_iterations, n_edited,
  * n_quantized, n_lossless, residual_violations, converged, stalled, status.
  * log (may be NULL) receives up to log_cap records of 16 int64:
  *   kind (1 = C, 2 = S), FP0, FN0, FP1, FN1, FP2, FN2, FP3, FN3, TM_desc, TM_asc,
- *   |R|, changed, 0, 0, 0.
+ *   |R|, changed, TM_ss (saddle-saddle troublemakers), 0, 0.
  * status: 0 ok, 1 not converged (stalled or max_iters), -1 invalid, -2 bound, -3 nonfinite. */
-int oracle_correct(const ocx *cx, const float *f, const float *g_hat, float xi, int tier,
+int oracle_correct(const ocx *cx, const float *f, const float *g_hat, float xi, int tier, int ss,
                    int q_max, int64_t max_iters, float *g_out, uint8_t *q_out, int64_t *stats,
                    int64_t *log, int64_t log_cap);
 
 /* Violations of g against f as the correction loop sees them: cells whose criticality differs,
- * else (tier >= 3) the first differing cell of each separatrix branch the tier checks.  Writes
- * up to cap (dimension, id) pairs and returns the total. */
-int64_t oracle_residual(const ocx *cx, const float *f, const float *g, int tier, int64_t *dims, int64_t *ids,
-                        int64_t cap);
+ * else (tier >= 3) the first differing cell of each separatrix branch the tier checks (and, with
+ * ss at tier 4, the saddle-saddle troublemaker edges).  Writes up to cap (dimension, id) pairs
+ * and returns the total. */
+int64_t oracle_residual(const ocx *cx, const float *f, const float *g, int tier, int ss, int64_t *dims,
+                        int64_t *ids, int64_t cap);
 
 /* Decoder: g = lossless ? stored value : (g_hat - q*Delta) rounded once, Delta = xi*2^-q_max. */
 void oracle_decode(const float *g_hat, const uint8_t *q, int64_t n, const int64_t *idx,

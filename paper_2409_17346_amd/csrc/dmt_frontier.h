@@ -105,6 +105,14 @@ struct Ctl {
        step; inlist marks the members */                                                           \
     P(int) cand[2];                                                                                \
     P(uint8_t) inlist;                                                                             \
+    /* saddle-saddle connectors (3D, tier 4, DMT_F_SADDLE_SADDLE): the edges of f's 2-saddles,    \
+       two queues of edge ids for the walk down f's 1-2 V-paths, and per-edge stamps; edge id =  \
+       (c - 1) * n + anchor for the edge from anchor to anchor + c (c: direction bits 1..7) */      \
+    P(const int) ss_src;                                                                           \
+    P(int) ss_q[2];                                                                                \
+    P(unsigned) ss_stamp;                                                                          \
+    int n_ss_src;                                                                                  \
+    int ss_on;                                                                                     \
     float delta;                                                                                   \
     int q_max, tier;                                                                               \
     long long max_iters;
@@ -191,7 +199,9 @@ __device__ __forceinline__ unsigned long long violations(const FrontierView& B, 
     const Slot& s = slot_of(B, it);
     const unsigned long long ct = c_total(s);
     if (ct) return ct;
-    return B.tier >= 3 ? ld_relaxed(&s.cnt[CNT_TM_DESC]) + ld_relaxed(&s.cnt[CNT_TM_ASC]) : 0ull;
+    return B.tier >= 3 ? ld_relaxed(&s.cnt[CNT_TM_DESC]) + ld_relaxed(&s.cnt[CNT_TM_ASC]) +
+                             ld_relaxed(&s.cnt[CNT_TM_SS])
+                       : 0ull;
 }
 
 // ---- Equation 2 on one vertex, and the neighbourhood an edit makes dirty -------------------
@@ -732,6 +742,131 @@ __device__ __forceinline__ void phase_sapply(const FrontierView& B, const Dims& 
     block_add_counters<2>(slot_of<WG>(B, it).cnt + CNT_NREQ, rc);
 }
 
+// ---- saddle-saddle connectors (3D) --------------------------------------------------------
+
+// Id of the edge between adjacent vertices p and q: (c - 1) * n + anchor, with anchor the lower
+// of the two and c the direction bits of the step to the other.
+__device__ __forceinline__ int ss_edge_id(const Dims& dm, int p, int q) {
+    int px, py, pz, qx, qy, qz;
+    coords(dm, p, px, py, pz);
+    coords(dm, q, qx, qy, qz);
+    if (qx < px || qy < py || qz < pz) {
+        const int t = p; p = q; q = t;
+        const int dx = px - qx, dy = py - qy, dz = pz - qz;
+        return ((dx + 2 * dy + 4 * dz) - 1) * dm.n + p;
+    }
+    return ((qx - px + 2 * (qy - py) + 4 * (qz - pz)) - 1) * dm.n + p;
+}
+
+// Breadth-first walk of f's 1-2 V-paths from the edges of f's 2-saddles, by one workgroup of nt
+// threads (tid = thread index): an edge paired alike in f and g and with a triangle in f leads on
+// to the triangle's two other edges; an edge paired differently in g is a troublemaker, and
+// emit(target) gets the apex of its f-pair (edge ij paired with triangle ijk in f: k; edge ij
+// paired with vertex i in f: j); critical edges (1-saddles) and edges paired with a vertex end a
+// path.  Each edge is claimed once per walk by raising its stamp to `stamp`; the level queues
+// hold edge ids.  Whole waves call emit (target -1: none).  Returns this thread's troublemakers.
+template <class Emit>
+__device__ __forceinline__ int ss_walk(const uint8_t* fpl, const uint8_t* gpl, const Dims& dm, const int* src,
+                                       int n_src, int* q0, int* q1, unsigned* stamps, unsigned stamp, int tid,
+                                       int nt, Emit emit) {
+    __shared__ int ss_len[2];
+    int* q[2] = {q0, q1};
+    const int n = dm.n;
+    int found = 0;
+    if (tid == 0) { ss_len[0] = 0; ss_len[1] = 0; }
+    __syncthreads();
+    for (int base = 0; base < n_src; base += nt) {
+        if (wave_done(base, tid, n_src)) break;
+        const int i = base + tid;
+        int e = 0;
+        bool won = false;
+        if (i < n_src) {
+            e = src[i];
+            won = atomicMax(&stamps[e], stamp) < stamp;
+        }
+        const int k = wave_append(won, &ss_len[0]);
+        if (won) q0[k] = e;
+    }
+    __syncthreads();
+    int cur = 0;
+    for (;;) {
+        const int ncur = ss_len[cur];
+        if (ncur == 0) break;
+        if (tid == 0) ss_len[cur ^ 1] = 0;
+        __syncthreads();
+        for (int base = 0; base < ncur; base += nt) {
+            if (wave_done(base, tid, ncur)) break;
+            const int i = base + tid;
+            int target = -1, p0 = -1, p1 = -1;
+            if (i < ncur) {
+                const int e = q[cur][i];
+                const int c = e / n + 1;            // the edge's direction bits = its code plane
+                const int a = e - (c - 1) * n;
+                const uint8_t fc = fpl[(size_t)c * n + a], gc = gpl[(size_t)c * n + a];
+                if (fc != gc) {
+                    if (fc != CODE_CRIT) {
+                        target = a + c27_lin(dm, fc & 63);
+                        found++;
+                    }
+                } else if (fc & 0x40) {
+                    const int x = a + c27_lin(dm, fc & 63);
+                    const int w = a + (c & 1) + dm.nx * ((c >> 1) & 1) + dm.nxy * ((c >> 2) & 1);
+                    p0 = ss_edge_id(dm, a, x);
+                    p1 = ss_edge_id(dm, w, x);
+                }
+            }
+            const bool w0 = p0 >= 0 && atomicMax(&stamps[p0], stamp) < stamp;
+            const bool w1 = p1 >= 0 && atomicMax(&stamps[p1], stamp) < stamp;
+            const int k0 = wave_append(w0, &ss_len[cur ^ 1]);
+            if (w0) q[cur ^ 1][k0] = p0;
+            const int k1 = wave_append(w1, &ss_len[cur ^ 1]);
+            if (w1) q[cur ^ 1][k1] = p1;
+            emit(target);
+        }
+        __syncthreads();
+        cur ^= 1;
+    }
+    return found;
+}
+
+// The saddle-saddle part of the separatrix step of iteration it (called by one whole workgroup
+// after phase_sapply): troublemakers are requested and edited at once, like the branches'.
+template <bool WG>
+__device__ __forceinline__ void phase_ss(const FrontierView& B, const Dims& dm, int it, bool edit, int tid, int nt) {
+    int rc[2] = {0, 0};
+    int c = ss_walk(B.fpl, B.gpl, dm, B.ss_src, B.n_ss_src, B.ss_q[0], B.ss_q[1], B.ss_stamp, (unsigned)it + 1u,
+                    tid, nt, [&](int target) { request_apply<3, WG>(B, dm, target, it, edit, rc); });
+    block_add_counters<1>(slot_of<WG>(B, it).cnt + CNT_TM_SS, &c);
+    block_add_counters<2>(slot_of<WG>(B, it).cnt + CNT_NREQ, rc);
+}
+
+// Edges of f's 2-saddles (critical triangles, ids a * 12 + type): three per triangle into src.
+__global__ void __launch_bounds__(256) k_ss_sources(const int* __restrict__ crit2, int n2, Dims dm,
+                                                    int* __restrict__ src) {
+    constexpr auto& g = G<3>::g;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n2) return;
+    const int T = crit2[k];
+    const int a = T / g.ntypes[2];
+    const int p = g.base[2] + (T - a * g.ntypes[2]);
+    int v[3];
+    for (int j = 0; j < 3; j++) v[j] = a + g.bvert[p][j][0] + dm.nx * g.bvert[p][j][1] + dm.nxy * g.bvert[p][j][2];
+    src[3 * k] = ss_edge_id(dm, v[0], v[1]);
+    src[3 * k + 1] = ss_edge_id(dm, v[0], v[2]);
+    src[3 * k + 2] = ss_edge_id(dm, v[1], v[2]);
+}
+
+// The dense form's saddle-saddle walk: troublemaker targets into req, their count into cnt.
+__global__ void __launch_bounds__(1024) k_ss_dense(const uint8_t* __restrict__ fpl, const uint8_t* __restrict__ gpl,
+                                                   Dims dm, const int* __restrict__ src, int n_src, int* q0, int* q1,
+                                                   unsigned* stamps, unsigned stamp, uint8_t* __restrict__ req,
+                                                   unsigned long long* __restrict__ cnt) {
+    int c = ss_walk(fpl, gpl, dm, src, n_src, q0, q1, stamps, stamp, threadIdx.x, blockDim.x, [&](int target) {
+        if (target >= 0) req[target] = 1;
+    });
+    block_add_counters<1>(cnt + CNT_TM_SS, &c);
+}
+
 // ---- iteration bookkeeping ----------------------------------------------------------------
 
 // End state of iteration it from its counters (all threads agree): 0 go on, 1 converged,
@@ -763,7 +898,8 @@ __device__ __forceinline__ void record_iteration(const FrontierView& B, int it, 
         rec[16] = ld_relaxed(&S.n_db);
         rec[17] = ld_relaxed(&S.n_scan);
         rec[18] = it == 0 ? 0 : ld_relaxed(&S.n_tc);
-        for (int k = 19; k < DMT_LOG_WORDS; k++) rec[k] = 0;
+        rec[19] = 0;
+        rec[20] = (long long)ld_relaxed(&S.cnt[CNT_TM_SS]);
     }
     if (cstep) c->c_it++; else c->s_it++;
 }
@@ -817,7 +953,7 @@ __device__ __forceinline__ int wave_decide(const FrontierView& B, int it, int la
     const Slot& S = slot_of<WG>(B, it);
     const unsigned long long v = lane < CNT_WORDS ? ld_relaxed(&S.cnt[lane]) : 0ull;
     const unsigned long long cv = (lane >= CNT_FP0 && lane < CNT_FP0 + 8) ? v : 0ull;
-    const unsigned long long tv = (lane == CNT_TM_DESC || lane == CNT_TM_ASC) ? v : 0ull;
+    const unsigned long long tv = (lane == CNT_TM_DESC || lane == CNT_TM_ASC || lane == CNT_TM_SS) ? v : 0ull;
     unsigned long long ct = cv, tt = tv;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -825,6 +961,7 @@ __device__ __forceinline__ int wave_decide(const FrontierView& B, int it, int la
         tt += __shfl_xor(tt, o, 64);
     }
     const unsigned long long changed = __shfl(v, CNT_CHANGED, 64);
+    const unsigned long long tm_ss = __shfl(v, CNT_TM_SS, 64);
     const unsigned long long viol = ct ? ct : (B.tier >= 3 ? tt : 0ull);
     int st = 0;
     if (viol == 0) st = 1;
@@ -841,6 +978,7 @@ __device__ __forceinline__ int wave_decide(const FrontierView& B, int it, int la
         else if (lane == 16) rec[16] = ld_relaxed(&S.n_db);
         else if (lane == 17) rec[17] = ld_relaxed(&S.n_scan);
         else if (lane == 18) rec[18] = ld_relaxed(&S.n_tc);
+        else if (lane == 20) rec[20] = (long long)tm_ss;
     }
     if (lane == 0) {
         if (st == 2 || st == 3) c->residual = (long long)viol;
@@ -901,6 +1039,12 @@ __device__ __forceinline__ void run_job_wg(const FrontierView& B, int max_passes
         if (sstep_sh) {
             phase_sapply<D, true>(B, dm, it, (long long)it != B.max_iters, tid, nt);
             __syncthreads();
+            if constexpr (D == 3) {
+                if (B.ss_on && B.tier == 4) {
+                    phase_ss<true>(B, dm, it, (long long)it != B.max_iters, tid, nt);
+                    __syncthreads();
+                }
+            }
         }
         if (tid < 64) {
             const int st = wave_decide<true>(B, it, tid);
@@ -1039,6 +1183,14 @@ __global__ void __launch_bounds__(256) k_fr_sapply(FrontierBufs hb, Dims dm) {
     if (!running(B.ctl) || B.tier < 3 || c_total(slot_of(B, it)) != 0) return;
     phase_sapply<D>(B, dm, it, (long long)it != B.max_iters, blockIdx.x * blockDim.x + threadIdx.x,
                     gridDim.x * blockDim.x);
+}
+
+// The saddle-saddle walk of a job's separatrix step as one workgroup (phase and hand-off forms).
+__global__ void __launch_bounds__(1024) k_fr_ss(FrontierBufs hb, Dims dm) {
+    const FrontierView& B = view(hb);
+    const int it = ld_relaxed(&B.ctl->it);
+    if (!running(B.ctl) || B.tier < 4 || !B.ss_on || c_total(slot_of(B, it)) != 0) return;
+    phase_ss<false>(B, dm, it, (long long)it != B.max_iters, threadIdx.x, blockDim.x);
 }
 
 __global__ void k_fr_finish(FrontierBufs hb) {

@@ -92,12 +92,14 @@ struct MscBufs {
 struct JobWs {
     DevBuf lo, g0, g1, state, fpl, gpl, vmask, vl0, vl1, dvl0, dvl1, dal0, dal1, vstamp, astamp, astamp1, rstamp;
     DevBuf vpos, vstart, tsum, toff, ecell, bstamp, tcl, dbl, newmin, cand0, cand1, inlist;
+    DevBuf ss_src, ss_q0, ss_q1, ss_stamp;
     MscBufs msc;
     std::vector<DevBuf*> all() {
         std::vector<DevBuf*> v = {&lo,     &g0,     &g1,      &state,  &fpl,   &gpl,   &vmask,  &vl0,
                                   &vl1,    &dvl0,   &dvl1,    &dal0,   &dal1,  &vstamp, &astamp, &astamp1,
                                   &rstamp, &vpos,   &vstart,  &tsum,   &toff,   &ecell, &bstamp, &tcl,
-                                  &dbl,    &newmin, &cand0,   &cand1,  &inlist};
+                                  &dbl,    &newmin, &cand0,   &cand1,  &inlist, &ss_src, &ss_q0,  &ss_q1,
+                                  &ss_stamp};
         for (DevBuf* b : msc.all()) v.push_back(b);
         return v;
     }
@@ -245,7 +247,8 @@ dmt_status check_options(dmt_context* c, const dmt_options* o, float xi) {
     if (!o) return fail(c, DMT_E_INVALID, "options are NULL");
     if (o->tier < 1 || o->tier > 4) return fail(c, DMT_E_INVALID, "tier must be 1..4");
     if (o->q_max < 0 || o->q_max > 7) return fail(c, DMT_E_INVALID, "q_max must be 0..7");
-    if (o->flags & ~(uint32_t)(DMT_F_DENSE | DMT_F_PHASES)) return fail(c, DMT_E_INVALID, "unknown flags");
+    if (o->flags & ~(uint32_t)(DMT_F_DENSE | DMT_F_PHASES | DMT_F_SADDLE_SADDLE))
+        return fail(c, DMT_E_INVALID, "unknown flags");
     if (!(xi > 0.0f) || !std::isfinite(xi)) return fail(c, DMT_E_INVALID, "xi must be finite and > 0");
     if (!(ldexpf(xi, -o->q_max) >= FLT_MIN)) return fail(c, DMT_E_INVALID, "xi / 2^q_max is not a normal float");
     return DMT_OK;
@@ -470,6 +473,30 @@ dmt_status job_setup(dmt_context* c, Job& J, unsigned* flag, hipStream_t st) {
     return launch_grad(c, D, J.f, P<uint8_t>(w.fpl), J.dm, st);
 }
 
+// Saddle-saddle state of a 3D tier-4 job with DMT_F_SADDLE_SADDLE (f's branches built): the edges
+// of f's 2-saddles, the two walk queues (each level holds distinct edges, at most 7 per vertex)
+// and zeroed edge stamps.  Returns whether the job walks its connectors.
+template <int D>
+dmt_status ss_setup(dmt_context* c, Job& J, bool& on, hipStream_t st) {
+    on = false;
+    if (D != 3 || J.o.tier != 4 || !(J.o.flags & DMT_F_SADDLE_SADDLE)) return DMT_OK;
+    JobWs& w = *J.w;
+    const int64_t n = J.dm.n;
+    const int64_t n2 = w.msc.ncrit[2];
+    if (7 * n >= (int64_t)INT32_MAX) return fail(c, DMT_E_INVALID, "grid too large for the saddle-saddle walk");
+    ENSURE(c, w.ss_src, sizeof(int) * (size_t)(3 * n2));
+    ENSURE(c, w.ss_q0, sizeof(int) * (size_t)(7 * n));
+    ENSURE(c, w.ss_q1, sizeof(int) * (size_t)(7 * n));
+    ENSURE(c, w.ss_stamp, sizeof(unsigned) * (size_t)(7 * n));
+    HIPCHK(c, hipMemsetAsync(w.ss_stamp.p, 0, sizeof(unsigned) * (size_t)(7 * n), st));
+    if (n2) {
+        k_ss_sources<<<nblocks(n2), TPB, 0, st>>>(P<int>(w.msc.crit[2]), (int)n2, J.dm, P<int>(w.ss_src));
+        CHECK_LAUNCH(c);
+    }
+    on = true;
+    return DMT_OK;
+}
+
 // a2 (f-branches), frontier buffers and control block of a job whose setup passed; fills J.B.
 template <int D>
 dmt_status job_frontier(dmt_context* c, Job& J, Ctl* ctl, hipStream_t st) {
@@ -580,6 +607,16 @@ dmt_status job_frontier(dmt_context* c, Job& J, Ctl* ctl, hipStream_t st) {
         B.cand[1] = P<int>(w.cand1);
         B.inlist = P<uint8_t>(w.inlist);
     }
+    bool ss = false;
+    if (w.msc.valid) TRY(ss_setup<D>(c, J, ss, st));
+    if (ss) {
+        B.ss_src = P<int>(w.ss_src);
+        B.n_ss_src = (int)(3 * w.msc.ncrit[2]);
+        B.ss_q[0] = P<int>(w.ss_q0);
+        B.ss_q[1] = P<int>(w.ss_q1);
+        B.ss_stamp = P<unsigned>(w.ss_stamp);
+        B.ss_on = 1;
+    }
     B.delta = ldexpf(J.xi, -J.o.q_max);
     B.q_max = J.o.q_max;
     B.tier = J.o.tier;
@@ -638,6 +675,7 @@ dmt_status grid_iterations(dmt_context* c, const FrontierBufs& B, const Dims& dm
     if (from_sstep) {
         // paused before the troublemaker pass of iteration ctl->it: finish that iteration first
         k_fr_sapply<D><<<gfull, TPB, 0, st>>>(B, dm);
+        if (B.ss_on) k_fr_ss<<<1, 1024, 0, st>>>(B, dm);
         k_fr_finish<<<1, 1, 0, st>>>(B);
     }
     for (int k = 0; k <= K; k++) {
@@ -646,6 +684,7 @@ dmt_status grid_iterations(dmt_context* c, const FrontierBufs& B, const Dims& dm
         if (B.tier >= 3) k_fr_bscan<D><<<gfull, TPB, 0, st>>>(B, dm);
         if (k == K) break;
         if (B.tier >= 3) k_fr_sapply<D><<<gfull, TPB, 0, st>>>(B, dm);
+        if (B.ss_on) k_fr_ss<<<1, 1024, 0, st>>>(B, dm);
         k_fr_finish<<<1, 1, 0, st>>>(B);
     }
     CHECK_LAUNCH(c);
@@ -843,6 +882,7 @@ dmt_status run_phases(dmt_context* c, Job& J, hipStream_t st) {
         const int64_t nbr = (int64_t)J.B.n_desc + J.B.n_asc;
         if (nbr) k_fr_cand_init<<<nblocks(nbr), TPB, 0, st>>>(J.B, J.B.ctl);
         if (J.o.tier >= 3) k_fr_sapply<D><<<gfull, TPB, 0, st>>>(J.B, J.dm);
+        if (J.B.ss_on) k_fr_ss<<<1, 1024, 0, st>>>(J.B, J.dm);
         k_fr_finish<<<1, 1, 0, st>>>(J.B);
         CHECK_LAUNCH(c);
     }
@@ -858,6 +898,7 @@ dmt_status run_phases(dmt_context* c, Job& J, hipStream_t st) {
                 k_fr_bscan<D><<<gfull, TPB, 0, st>>>(J.B, J.dm);
                 k_fr_sapply<D><<<gfull, TPB, 0, st>>>(J.B, J.dm);
             }
+            if (J.B.ss_on) k_fr_ss<<<1, 1024, 0, st>>>(J.B, J.dm);
             k_fr_finish<<<1, 1, 0, st>>>(J.B);
             CHECK_LAUNCH(c);
         }
@@ -931,6 +972,8 @@ dmt_status dense_loop(dmt_context* c, Job& J, Ctl& out, hipStream_t st) {
     MscBufs& m = w.msc;
     m.valid = false;
     if (tier >= 3) TRY(build_msc<D>(c, m, fpl, dm, false, st));
+    bool ss = false;
+    if (tier >= 3) TRY(ss_setup<D>(c, J, ss, st));
     c->log.clear();
     int64_t it = 0, c_it = 0, s_it = 0, residual = 0;
     int done = 0;
@@ -962,8 +1005,12 @@ dmt_status dense_loop(dmt_context* c, Job& J, Ctl& out, hipStream_t st) {
                                                                req, cnt);
                 CHECK_LAUNCH(c);
             }
+            if (ss)
+                k_ss_dense<<<1, 1024, 0, st>>>(fpl, gpl, dm, P<int>(w.ss_src), (int)(3 * m.ncrit[2]), P<int>(w.ss_q0),
+                                               P<int>(w.ss_q1), P<unsigned>(w.ss_stamp), (unsigned)it + 1u, req, cnt);
+            CHECK_LAUNCH(c);
             TRY(read_counters(c, st));
-            viol = (int64_t)(c->hcnt[CNT_TM_DESC] + c->hcnt[CNT_TM_ASC]);
+            viol = (int64_t)(c->hcnt[CNT_TM_DESC] + c->hcnt[CNT_TM_ASC] + c->hcnt[CNT_TM_SS]);
         }
         if (viol == 0) { done = 1; break; }
         if (it == max_iters) {
@@ -980,6 +1027,7 @@ dmt_status dense_loop(dmt_context* c, Job& J, Ctl& out, hipStream_t st) {
         int64_t rec[DMT_LOG_WORDS] = {0};
         rec[0] = kind;
         for (int k = 1; k <= CNT_CHANGED; k++) rec[k] = (int64_t)c->hcnt[k];
+        rec[20] = (int64_t)c->hcnt[CNT_TM_SS];
         c->log.insert(c->log.end(), rec, rec + DMT_LOG_WORDS);
         it++;
         if (kind == 1) c_it++; else s_it++;
@@ -1074,10 +1122,13 @@ namespace {
 constexpr int ROUND_PASSES = 512;
 constexpr int SERVER_LANES = 4;   // worker lanes of a server (streams whose jobs overlap on the device)
 
-int64_t workspace_estimate(int D, int64_t n) {
+int64_t workspace_estimate(int D, int64_t n, const dmt_options* o = nullptr) {
     // fields, state, f and g planes, frontier lists and stamps, separatrix branches (an upper
-    // estimate of what the correction of one field allocates; the branches are data-dependent)
-    return (D == 2 ? 112 : 224) * n + (1 << 20);
+    // estimate of what the correction of one field allocates; the branches are data-dependent),
+    // and the saddle-saddle walk's two level queues and edge stamps (7 edges per vertex, 4 B each)
+    int64_t est = (D == 2 ? 112 : 224) * n + (1 << 20);
+    if (o && D == 3 && o->tier == 4 && (o->flags & DMT_F_SADDLE_SADDLE)) est += 84 * n;
+    return est;
 }
 
 // Device bytes a workspace holds now.
@@ -1605,9 +1656,9 @@ dmt_status dmt_correct_noalloc(dmt_context* c, const dmt_grid* gr, const float* 
     TRY(check_grid(c, gr, dm, D));
     TRY(check_options(c, o, xi));
     if (!c->scratch) return fail(c, DMT_E_HIP, "no scratch on this device: " + c->scratch_err);
-    if (workspace_estimate(D, dm.n) > (int64_t)DMT_NOALLOC_SCRATCH_BYTES)
+    if (workspace_estimate(D, dm.n, o) > (int64_t)DMT_NOALLOC_SCRATCH_BYTES)
         return fail(c, DMT_E_NOMEM, "field of " + std::to_string((long long)dm.n) + " vertices needs about " +
-                                        std::to_string((long long)workspace_estimate(D, dm.n)) +
+                                        std::to_string((long long)workspace_estimate(D, dm.n, o)) +
                                         " bytes of scratch; the allocation-free path holds " +
                                         std::to_string((long long)DMT_NOALLOC_SCRATCH_BYTES));
     // Every buffer this call uses starts empty, so ensure() carves it from the scratch arena; the
@@ -1682,7 +1733,8 @@ dmt_status dmt_correct_batch(dmt_context* c, int32_t n_jobs, dmt_job* jobs_host,
         Job J;
         dmt_status s = check_grid(c, &h.grid, J.dm, J.D);
         if (s == DMT_OK) s = check_options(c, &h.opts, h.xi);
-        if (s == DMT_OK && h.opts.flags != 0) s = fail(c, DMT_E_INVALID, "batched jobs take no flags");
+        if (s == DMT_OK && (h.opts.flags & ~(uint32_t)DMT_F_SADDLE_SADDLE))
+            s = fail(c, DMT_E_INVALID, "batched jobs take no flags but DMT_F_SADDLE_SADDLE");
         if (s == DMT_OK && (!h.f || !h.g_hat || !h.g_out || !h.q_out)) s = fail(c, DMT_E_INVALID, "null argument");
         h.status = s;
         if (s != DMT_OK) continue;
@@ -1889,7 +1941,7 @@ int64_t dmt_workspace_bytes(const dmt_grid* gr, const dmt_options* o) {
     Dims dm;
     int D;
     if (check_grid(nullptr, gr, dm, D) != DMT_OK) return -1;
-    return workspace_estimate(D, dm.n);
+    return workspace_estimate(D, dm.n, o);
 }
 
 dmt_status dmt_server_create(dmt_server** out, int hip_device, int64_t hbm_budget_bytes, int32_t max_jobs) {
@@ -1964,11 +2016,11 @@ dmt_status dmt_server_submit(dmt_server* s, const dmt_job* job, int64_t* ticket)
     Job& J = t.J;
     dmt_status rc = check_grid(nullptr, &job->grid, J.dm, J.D);
     if (rc == DMT_OK) rc = check_options(nullptr, &job->opts, job->xi);
-    if (rc == DMT_OK && job->opts.flags != 0) rc = DMT_E_INVALID;
+    if (rc == DMT_OK && (job->opts.flags & ~(uint32_t)DMT_F_SADDLE_SADDLE)) rc = DMT_E_INVALID;
     if (rc == DMT_OK && (!job->f || !job->g_hat || !job->g_out || !job->q_out)) rc = DMT_E_INVALID;
     if (rc != DMT_OK) return rc;
     J.f = job->f; J.gh = job->g_hat; J.xi = job->xi; J.o = job->opts; J.g_out = job->g_out; J.q_out = job->q_out;
-    t.bytes = workspace_estimate(J.D, J.dm.n);
+    t.bytes = workspace_estimate(J.D, J.dm.n, &job->opts);
     {
         std::lock_guard<std::mutex> lk(s->mu);
         if (s->stop) return DMT_E_INVALID;

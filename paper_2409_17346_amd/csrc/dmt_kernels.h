@@ -33,7 +33,9 @@ struct Dims {
 enum {
     CNT_KIND = 0, CNT_FP0 = 1,  // FP_d = 1 + 2d, FN_d = 2 + 2d
     CNT_TM_DESC = 9, CNT_TM_ASC = 10, CNT_NREQ = 11, CNT_CHANGED = 12,
-    CNT_EDITED = 13, CNT_QUANT = 14, CNT_LOSSLESS = 15, CNT_WORDS = 16
+    CNT_EDITED = 13, CNT_QUANT = 14, CNT_LOSSLESS = 15,
+    CNT_TM_SS = 16,   // saddle-saddle troublemakers (log word 20)
+    CNT_WORDS = 17
 };
 
 __device__ __forceinline__ int c27_lin(const Dims& d, int c) {

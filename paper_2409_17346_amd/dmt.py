@@ -26,7 +26,7 @@ DMT_E_NOMEM = -4
 DMT_NOALLOC_SCRATCH_BYTES = 134217728   # include/dmt.h: scratch of dmt_correct_noalloc per GPU
 STATUS_NAMES = {0: "ok", 1: "not_converged", 2: "pending", -1: "invalid", -2: "bound", -3: "nonfinite",
                 -4: "nomem", -5: "hip"}
-LOG_WORDS = 20
+LOG_WORDS = 21
 LOG_KEYS = ["kind", "FP0", "FN0", "FP1", "FN1", "FP2", "FN2", "FP3", "FN3", "TM_desc", "TM_asc", "n_req",
             "changed", "dirty_vertices", "affected_anchors", "listed_anchors", "branches_settled",
             "branch_cells_examined", "branch_cells_touched", "ticks"]
@@ -275,6 +275,7 @@ class Result:
 
 DMT_F_DENSE = 1
 DMT_F_PHASES = 2
+DMT_F_SADDLE_SADDLE = 4
 
 
 def dmt_correct(ctx: Context, f: torch.Tensor, g_hat: torch.Tensor, xi: float, tier: int = 4, q_max: int = 6,
@@ -440,7 +441,7 @@ def dmt_get_tuning(ctx: Context) -> Dict[str, list]:
 
 
 def dmt_correct_batch(ctx: Context, fields, tier: int = 4, q_max: int = 6, max_iters: int = -1,
-                      outputs=None, lossless: bool = True):
+                      outputs=None, lossless: bool = True, flags: int = 0):
     """Corrects a list of (f, g_hat, xi) jobs together.  Returns a list of Result (lossless edits
     read by the library from q == 0xFF unless lossless is False; no per-iteration log)."""
     n = len(fields)
@@ -459,7 +460,7 @@ def dmt_correct_batch(ctx: Context, fields, tier: int = 4, q_max: int = 6, max_i
         arr[j].f = f.data_ptr()
         arr[j].g_hat = gh.data_ptr()
         arr[j].xi = xi
-        arr[j].opts = dmt_options(tier, q_max, max_iters, 0)
+        arr[j].opts = dmt_options(tier, q_max, max_iters, flags)
         arr[j].g_out = g_out.data_ptr()
         arr[j].q_out = q_out.data_ptr()
     st = _stream(fields[0][0]) if n else None
@@ -562,7 +563,8 @@ class Server:
         self._ctx = None   # context for reading lossless lists of finished jobs
 
     def submit(self, f: torch.Tensor, g_hat: torch.Tensor, xi: float, tier: int = 4, q_max: int = 6,
-               max_iters: int = -1, g_out: Optional[torch.Tensor] = None, q_out: Optional[torch.Tensor] = None) -> int:
+               max_iters: int = -1, g_out: Optional[torch.Tensor] = None, q_out: Optional[torch.Tensor] = None,
+               flags: int = 0) -> int:
         _dev(f)
         _dev(g_hat)
         if g_out is None:
@@ -572,7 +574,7 @@ class Server:
         j = dmt_job()
         j.grid = grid_of(f)
         j.f, j.g_hat, j.xi = f.data_ptr(), g_hat.data_ptr(), xi
-        j.opts = dmt_options(tier, q_max, max_iters, 0)
+        j.opts = dmt_options(tier, q_max, max_iters, flags)
         j.g_out, j.q_out = g_out.data_ptr(), q_out.data_ptr()
         torch.cuda.current_stream(f.device).synchronize()   # inputs complete before the server reads them
         t = C.c_int64()

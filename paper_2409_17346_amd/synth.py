@@ -222,7 +222,7 @@ def lognormal3d(side: int, seed: int, rng: np.random.Generator | None = None,
     amp = np.zeros_like(k)
     nz = k > 0
     amp[nz] = k[nz] ** (slope / 2.0)
-    field = np.fft.irfftn(spec * amp, s=(side, side, side))
+    field = np.fft.irfftn(spec * amp, s=(side, side, side), axes=(0, 1, 2))
     field = (field - field.mean()) / field.std()
     return np.exp(field).astype(np.float32)
 

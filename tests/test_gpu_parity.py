@@ -93,7 +93,8 @@ def _compare_correction(ctx, dmt, w, tier=None, q_max=None, max_iters=-1, flags=
     nx, ny, nz = w.dims
     cx = oracle.Complex.grid(nx, ny, nz)
     o = oracle.correct(cx, w.f.reshape(-1), w.g_hat.reshape(-1), w.xi, tier, q_max,
-                       max_iters=(1 << 40) if max_iters < 0 else max_iters)
+                       max_iters=(1 << 40) if max_iters < 0 else max_iters,
+                       saddle_saddle=bool(flags & dmt.DMT_F_SADDLE_SADDLE))
     r = dmt.dmt_correct(ctx, _t(w.f), _t(w.g_hat), w.xi, tier, q_max, max_iters, flags=flags)
     assert r.status == o["status"]
     for k, v in o["stats"].items():
@@ -104,6 +105,7 @@ def _compare_correction(ctx, dmt, w, tier=None, q_max=None, max_iters=-1, flags=
     assert np.array_equal(r.lossless_idx.cpu().numpy(), o["lossless_idx"])
     assert np.array_equal(r.lossless_val.cpu().numpy().view(np.uint32), o["lossless_val"].view(np.uint32))
     assert np.array_equal(r.log.numpy()[:, :13], o["log"][:, :13])
+    assert np.array_equal(r.log.numpy()[:, 20], o["log"][:, 13])     # saddle-saddle troublemakers
     # decoder reproduces the corrected field
     dec = dmt.dmt_apply_edits(ctx, _t(w.g_hat), r.q, r.lossless_idx, r.lossless_val, w.xi, q_max)
     assert torch.equal(dec.view(torch.int32), r.g.view(torch.int32))
@@ -586,3 +588,49 @@ def test_tier_study_field(ctx, dmt, tier):
         assert a["separatrix_recall_connectivity"] == 1.0
     if tier == 4:
         assert a["separatrix_recall"] == a["separatrix_precision"] == 1.0
+
+
+SS_GPU_CASES = [((4, 4, 5), "smooth", 0), ((4, 5, 5), "smooth", 4), ((4, 5, 6), "uniform", 6),
+                ((4, 5, 6), "smooth", 10), ((9, 10, 12), "smooth", 13), ((17, 11, 23), "uniform", 2)]
+
+
+@pytest.mark.parametrize("shape,kind,seed", SS_GPU_CASES)
+@FORMS
+def test_saddle_saddle(ctx, dmt, shape, kind, seed, flags):
+    """Tier 4 with saddle-saddle connectors (3D): the oracle's results and log in every form."""
+    w = synth.tiny_cases(seed, shape, rel=0.2 if max(shape) < 8 else 0.05, kind=kind, ghat="noise")
+    r, o = _compare_correction(ctx, dmt, w, tier=4, flags=flags | dmt.DMT_F_SADDLE_SADDLE)
+    if max(shape) < 8:
+        assert o["log"][:, 13].sum() > 0
+
+
+@pytest.mark.parametrize("case", ["lognormal32", "lognormal48"])
+def test_saddle_saddle_fields(ctx, dmt, case):
+    w = synth.lognormal_case(32, 3) if case == "lognormal32" else synth.lognormal_case(48, 4)
+    r, o = _compare_correction(ctx, dmt, w, tier=4, flags=dmt.DMT_F_SADDLE_SADDLE)
+    assert r.status == "ok" and o["log"][:, 13].sum() > 0
+
+
+@pytest.mark.parametrize("limit", [1, 64])
+def test_saddle_saddle_handoff(ctx, dmt, limit):
+    """Saddle-saddle walks in the full-grid hand-off iterations (a one-workgroup launch)."""
+    w = synth.tiny_cases(13, (12, 10, 9), rel=0.05, kind="smooth", ghat="noise")
+    dmt.dmt_set_tuning(ctx, {"loop_threads": [1024, 512], "handoff_anchors": [limit, limit],
+                             "grid_iterations": [4, 64]})
+    try:
+        _compare_correction(ctx, dmt, w, tier=4, flags=dmt.DMT_F_SADDLE_SADDLE)
+    finally:
+        dmt.dmt_set_tuning(ctx, None)
+
+
+def test_saddle_saddle_batch_and_2d(ctx, dmt):
+    """The option in a batch (3D jobs walk their connectors, 2D jobs are unchanged)."""
+    ws = [synth.tiny_cases(13, (12, 10, 9), rel=0.05, kind="smooth", ghat="noise"),
+          synth.tiny_cases(0, (4, 4, 5), rel=0.2, kind="smooth", ghat="noise"), synth.config_small2d()]
+    res = dmt.dmt_correct_batch(ctx, [(_t(w.f), _t(w.g_hat), w.xi) for w in ws], tier=4,
+                                flags=dmt.DMT_F_SADDLE_SADDLE)
+    for w, r in zip(ws, res):
+        o = oracle.correct(oracle.Complex.grid(*w.dims), w.f.reshape(-1), w.g_hat.reshape(-1), w.xi, 4, 6,
+                           saddle_saddle=True)
+        assert r.status == o["status"]
+        assert np.array_equal(r.g.cpu().numpy().reshape(-1).view(np.uint32), o["g"].view(np.uint32)), w.name

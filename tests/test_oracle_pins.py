@@ -691,3 +691,56 @@ def test_edit_stream_decodes_a_correction():
     idx = np.nonzero(q == 0xFF)[0]
     g = oracle.decode(w.g_hat.reshape(-1), q, idx, o["g"][idx], w.xi, 6)
     assert np.array_equal(g.view(np.uint32), o["g"].view(np.uint32))
+
+
+# ------------------------------------------------------------------------------------------
+# Saddle-saddle connectors (3D, Section 3.1 / Section 4.4 1-dimensional troublemakers)
+
+SS_CASES = [((5, 4, 4), "smooth", 0), ((5, 4, 4), "smooth", 8), ((5, 5, 4), "smooth", 4),
+            ((5, 5, 4), "smooth", 10), ((6, 5, 4), "uniform", 6), ((6, 5, 4), "smooth", 10),
+            ((4, 4, 4), "uniform", 3), ((5, 5, 5), "uniform", 1)]
+
+
+@pytest.mark.parametrize("shape,kind,seed", SS_CASES)
+def test_saddle_saddle_troublemakers_match_brute_force(shape, kind, seed):
+    """On a field whose critical cells already agree with f (a tier-2 correction), the oracle's
+    saddle-saddle troublemakers are the edges a literal walk of the brute-force 1-2 V-paths finds."""
+    nx, ny, nz = shape
+    cx = oracle.Complex.grid(nx, ny, nz)
+    cells = brute.kuhn_complex(shape)
+    w = synth.tiny_cases(seed, (nz, ny, nx), rel=0.2, kind=kind, ghat="noise")
+    f = w.f.reshape(-1)
+    g2 = oracle.correct(cx, f, w.g_hat.reshape(-1), w.xi, 2, 6)["g"]
+    res = oracle.residual(cx, f, g2, 4, saddle_saddle=True)
+    ids = {frozenset(cx.vertices(1, e)): e for e in range(cx.ncell[1]) if cx.vertices(1, e)}
+    assert set(int(i) for d, i in res if d == 1) == {ids[e] for e in brute.ss_troublemakers(cells, f, g2)}
+
+
+@pytest.mark.parametrize("shape,kind,seed", SS_CASES[:6])
+def test_saddle_saddle_connectors_preserved(shape, kind, seed):
+    """With the saddle-saddle option a converged tier-4 correction has exactly f's connectors
+    (every V-path from a 2-saddle to a 1-saddle, enumerated by brute force); the listed cases are
+    ones where tier 4 without the option leaves some connector different."""
+    nx, ny, nz = shape
+    cx = oracle.Complex.grid(nx, ny, nz)
+    cells = brute.kuhn_complex(shape)
+    w = synth.tiny_cases(seed, (nz, ny, nx), rel=0.2, kind=kind, ghat="noise")
+    f, gh = w.f.reshape(-1), w.g_hat.reshape(-1)
+    cf = brute.connectors(cells, f)
+    o = oracle.correct(cx, f, gh, w.xi, 4, 6, saddle_saddle=True)
+    assert o["status"] == "ok"
+    assert brute.connectors(cells, o["g"]) == cf
+    assert brute.msc(cells, o["g"])["desc"] == brute.msc(cells, f)["desc"]
+    assert o["log"][:, 13].sum() > 0 or len(cf) == 0
+    plain = oracle.correct(cx, f, gh, w.xi, 4, 6)
+    assert plain["status"] == "ok" and brute.connectors(cells, plain["g"]) != cf
+    # the option changes nothing in 2D or below tier 4
+    if seed == 0:
+        w2 = synth.tiny_cases(seed, (9, 8), rel=0.2, kind=kind, ghat="noise")
+        cx2 = oracle.Complex.grid(8, 9, 1)
+        a = oracle.correct(cx2, w2.f, w2.g_hat, w2.xi, 4, 6, saddle_saddle=True)
+        b = oracle.correct(cx2, w2.f, w2.g_hat, w2.xi, 4, 6)
+        assert np.array_equal(a["g"].view(np.uint32), b["g"].view(np.uint32))
+        a = oracle.correct(cx, f, gh, w.xi, 3, 6, saddle_saddle=True)
+        b = oracle.correct(cx, f, gh, w.xi, 3, 6)
+        assert np.array_equal(a["g"].view(np.uint32), b["g"].view(np.uint32))
