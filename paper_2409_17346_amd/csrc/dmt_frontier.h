@@ -32,6 +32,7 @@ struct Slot {
     int n_tc;               // branch cells of f on a dirty vertex whose codes changed (touched)
     int n_db;               // branches with a touched cell
     int n_scan;             // branch cells examined to settle those branches
+    int n_frz;              // listed anchors frozen by this iteration (freeze list length)
 };
 
 struct Ctl {
@@ -43,6 +44,12 @@ struct Ctl {
     int c_it, s_it;
     long long residual;
     unsigned long long ph[3];   // wall-clock ticks in the resident loop: troublemaker, gradient, violation passes
+    // frozen anchors (violations whose every target is floored, see freeze_pass): their
+    // violations by type, the number of distinct vertices they request, ftgt entries in use
+    unsigned long long dead_cnt[8];
+    unsigned long long dead_distinct;
+    int n_ftgt;
+    int n_dead;             // frozen anchors (in LDS while the resident loop runs)
     Slot slot[3];
 };
 
@@ -75,6 +82,13 @@ struct Ctl {
        iteration k mark [(k+1) & 1] while [k & 1] is still read */                                 \
     P(unsigned) astamp[2];                                                                         \
     P(unsigned) rstamp;       /* request stamps */                                                 \
+    /* frozen anchors: per anchor the offset of its targets in ftgt (ftgt_cap entries), per       \
+       vertex the number of frozen violations requesting it, and an iteration's freeze list */     \
+    P(int) fofs;                                                                                   \
+    P(int) ftgt;                                                                                   \
+    P(unsigned) dreq;                                                                              \
+    P(int) frz;                                                                                    \
+    int ftgt_cap;                                                                                  \
     P(long long) log;         /* DMT_LOG_WORDS per iteration */                                    \
     int log_cap;              /* records log can hold */                                           \
     int ndim;                 /* 2 or 3 */                                                         \
@@ -180,11 +194,19 @@ __device__ __forceinline__ bool wave_done(int base, int gtid, int n) {
 // from the job's control block when it starts and back when it stops); the full-grid phases
 // use the control block itself.
 __shared__ Slot wg_slots[3];
+__shared__ int wg_n_dead;
 
 template <bool WG = false>
 __device__ __forceinline__ Slot& slot_of(const FrontierView& B, int it) {
     if constexpr (WG) return wg_slots[it % 3];
     else return B.ctl->slot[it % 3];
+}
+
+// Number of frozen anchors of the job (the resident loop keeps it in LDS).
+template <bool WG = false>
+__device__ __forceinline__ int* n_dead_of(const FrontierView& B) {
+    if constexpr (WG) return &wg_n_dead;
+    else return &B.ctl->n_dead;
 }
 
 __device__ __forceinline__ unsigned long long c_total(const Slot& s) {
@@ -331,9 +353,12 @@ __device__ __forceinline__ void mark_neighbourhood(const FrontierView& B, const 
 
 // Request of vertex v (v < 0: none) in iteration it: the first requester counts it in rc[0]
 // and, when edits are allowed, edits it (counted in rc[1]) and marks its neighbourhood.
+// With floored, *floored is cleared unless v is already at its floor (final).  With frozen (the
+// job has frozen anchors), a vertex that frozen violations request (dreq[v] > 0) is counted among
+// their distinct targets instead.
 template <int D, bool WG = false>
 __device__ __forceinline__ void request_apply(const FrontierView& B, const Dims& dm, int v, int it, bool edit,
-                                              int* rc) {
+                                              int* rc, bool* floored = nullptr, bool frozen = false) {
     const unsigned stamp = (unsigned)it + 1u;
     bool changed = false;
     if (v >= 0) {
@@ -341,8 +366,10 @@ __device__ __forceinline__ void request_apply(const FrontierView& B, const Dims&
         // the stamp winner edits v, so they are current whenever they are used)
         const uint8_t st = B.state[v];
         const float ghv = B.gh[v], l = B.lo[v];
+        const unsigned dq = frozen ? B.dreq[v] : 0u;
+        if (floored) *floored &= (st & 0x80) != 0;
         if (atomicMax(&B.rstamp[v], stamp) < stamp) {
-            rc[0]++;
+            if (dq == 0) rc[0]++;
             if (edit) changed = apply_vertex(B, v, it, st, ghv, l);
             if (changed) rc[1]++;
         }
@@ -351,6 +378,12 @@ __device__ __forceinline__ void request_apply(const FrontierView& B, const Dims&
 }
 
 // ---- violation mask of one anchor: planes whose criticality differs between f and g --------
+
+// vmask word: bits 0..25 the violating planes; VM_QUIET: every target of the anchor's violations
+// was at its floor when last requested; VM_DEAD: the anchor is frozen (its targets are in ftgt).
+constexpr uint32_t VM_PLANES = (1u << 26) - 1u;
+constexpr uint32_t VM_QUIET = 1u << 30;
+constexpr uint32_t VM_DEAD = 1u << 31;
 
 // Every plane's codes are loaded unconditionally (plane P of anchor a is in bounds for every
 // anchor), so all loads are in flight together; planes whose cell does not exist, or that the
@@ -452,9 +485,11 @@ __device__ __forceinline__ int plane_target_any(int p, const FrontierView& B, co
 
 // Requests (and, with edit, edits) the targets of the violating planes m of anchor a.  Whole
 // waves call it; lanes without an anchor pass m = 0.  One plane per lane per round.
+// quiet is cleared unless every target is already at its floor.
 template <int D, bool WG = false>
 __device__ __forceinline__ void anchor_requests(const FrontierView& B, const Dims& dm, int a, uint32_t m, int it,
-                                                bool edit, int* cnt, int* rc) {
+                                                bool edit, int* cnt, int* rc, bool& quiet, bool frozen,
+                                                bool track_quiet) {
     const float* gcur = B.gb[it & 1];
     for (;;) {
         if (__ballot(m != 0) == 0) break;
@@ -464,8 +499,100 @@ __device__ __forceinline__ void anchor_requests(const FrontierView& B, const Dim
             m &= m - 1u;
             target = plane_target_any<D>(p, B, dm, a, gcur, cnt);
         }
-        request_apply<D, WG>(B, dm, target, it, edit, rc);
+        request_apply<D, WG>(B, dm, target, it, edit, rc, track_quiet ? &quiet : nullptr, frozen);
     }
+}
+
+// ---- frozen anchors ------------------------------------------------------------------------
+//
+// A violation whose target is at its floor requests it again every iteration and nothing
+// changes; near fp32 floor collisions hundreds of thousands of such violations can outlive every
+// other edit.  An anchor that stays listed (not affected) for a second iteration with every target
+// at its floor is frozen: it leaves the violation list, its targets are kept in ftgt, and its
+// violations are counted through per-type totals (dead_cnt) and the per-vertex request counts
+// (dreq, whose non-zero entries make up dead_distinct), which every iteration adds to its
+// counters exactly as if the anchor had requested its targets again.  When an edit affects a
+// frozen anchor, the gradient pass of the next iteration revives it (its counts are removed)
+// and the violation pass examines it afresh.  The log, the statistics and the output are those
+// of processing every violation every iteration.
+
+// dimension of the cells of plane p
+template <int D>
+__device__ __forceinline__ int plane_dim(int p) {
+    constexpr auto& g = G<D>::g;
+    int d = (p >= g.base[1]) + (p >= g.base[2]);
+    if constexpr (D == 3) d += (p >= g.base[3]);
+    return d;
+}
+
+// Revives the frozen anchors among iteration it's affected anchors.
+template <int D, bool WG = false>
+__device__ __forceinline__ void revive_pass(const FrontierView& B, const Dims& dm, int it, int gtid, int gsize) {
+    if (ld_relaxed(n_dead_of<WG>(B)) == 0) return;
+    const Slot& S = slot_of<WG>(B, it);
+    const int na = ld_relaxed(&S.n_da);
+    const int* alist = B.dal[it & 1];
+    int dc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int dd = 0, nr = 0;
+    for (int i = gtid; i < na; i += gsize) {
+        const int a = alist[i];
+        const uint32_t mv = B.vmask[a];
+        if (!(mv & VM_DEAD)) continue;
+        uint32_t m = mv & VM_PLANES;
+        B.vmask[a] = m;
+        nr++;
+        const int o = B.fofs[a];
+        for (int k = 0; m != 0; k++) {
+            const int p = __ffs(m) - 1;
+            m &= m - 1u;
+            const int d = plane_dim<D>(p);
+            dc[2 * d + (B.fpl[(size_t)p * dm.n + a] == CODE_CRIT ? 1 : 0)]++;
+            if (atomicSub(&B.dreq[B.ftgt[o + k]], 1u) == 1u) dd++;
+        }
+    }
+    for (int k = 0; k < 8; k++)
+        if (dc[k]) atomicAdd(&B.ctl->dead_cnt[k], (unsigned long long)(-(long long)dc[k]));
+    if (dd) atomicAdd(&B.ctl->dead_distinct, (unsigned long long)(-(long long)dd));
+    if (nr) atomicSub(n_dead_of<WG>(B), nr);
+}
+
+// Freezes the anchors the violation pass of iteration it listed for freezing: records their
+// targets (the same this iteration requested) and adds their violations to the frozen counts,
+// which iteration it + 1 onward uses.  With ftgt full the anchor stays in the violation list.
+template <int D, bool WG = false>
+__device__ __forceinline__ void freeze_pass(const FrontierView& B, const Dims& dm, int it, int gtid, int gsize) {
+    const Slot& S = slot_of<WG>(B, it);
+    const int nf = ld_relaxed(&S.n_frz);
+    const float* gcur = B.gb[it & 1];
+    int dc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int dd = 0, nz = 0;
+    for (int i = gtid; i < nf; i += gsize) {
+        const int a = B.frz[i];
+        uint32_t m = B.vmask[a] & VM_PLANES;
+        const int k = __popc(m);
+        // once ftgt is full no more space is taken (the counter stays far below 2^31)
+        int o = -1;
+        if (ld_relaxed(&B.ctl->n_ftgt) + k <= B.ftgt_cap) o = atomicAdd(&B.ctl->n_ftgt, k);
+        if (o < 0 || o + k > B.ftgt_cap) {
+            const int idx = atomicAdd(&slot_of<WG>(B, it + 1).n_vl, 1);
+            B.vl[(it + 1) & 1][idx] = a;
+            continue;
+        }
+        B.fofs[a] = o;
+        for (int j = 0; m != 0; j++) {
+            const int p = __ffs(m) - 1;
+            m &= m - 1u;
+            const int t = plane_target_any<D>(p, B, dm, a, gcur, dc);
+            B.ftgt[o + j] = t;
+            if (atomicAdd(&B.dreq[t], 1u) == 0u) dd++;
+        }
+        B.vmask[a] = (B.vmask[a] & VM_PLANES) | VM_DEAD;
+        nz++;
+    }
+    for (int k = 0; k < 8; k++)
+        if (dc[k]) atomicAdd(&B.ctl->dead_cnt[k], (unsigned long long)dc[k]);
+    if (dd) atomicAdd(&B.ctl->dead_distinct, (unsigned long long)dd);
+    if (nz) atomicAdd(n_dead_of<WG>(B), nz);
 }
 
 // ---- phases ------------------------------------------------------------------------------
@@ -478,7 +605,7 @@ __device__ __forceinline__ void phase_grad(const FrontierView& B, const Dims& dm
     if (gtid == 0) {
         Slot& s = slot_of<WG>(B, it + 1);
         for (int k = 0; k < CNT_WORDS; k++) s.cnt[k] = 0;
-        s.n_dv = s.n_da = s.n_vl = s.n_tc = s.n_db = s.n_scan = 0;
+        s.n_dv = s.n_da = s.n_vl = s.n_tc = s.n_db = s.n_scan = s.n_frz = 0;
     }
     const float* gcur = B.gb[it & 1];
     float* gnext = B.gb[(it + 1) & 1];
@@ -512,6 +639,7 @@ __device__ __forceinline__ void phase_grad(const FrontierView& B, const Dims& dm
             for (int e = e0; e < e1; e++) B.tcl[pos++] = B.ecell[e];
         }
     }
+    revive_pass<D, WG>(B, dm, it, gtid, gsize);
 }
 
 // First cell of f-branch k's cell range whose g pairing differs from f's, or INF32.
@@ -610,7 +738,12 @@ __device__ __forceinline__ void phase_bscan(const FrontierView& B, const Dims& d
 // Violation masks of the affected anchors (every anchor at iteration 0), the targets of every
 // violating anchor (edited at once when edit is set), the violation list of the next iteration,
 // and the speculative first-difference scan along f's branches.
-template <int D, bool WG = false>
+// Freezing (FREEZE) is done by the full-grid form, which runs the large iterations where many
+// violations are listed, and by the 3D resident loop (3D density fields collide at their floors
+// by the hundred thousand); the 2D resident loop keeps frozen anchors frozen and revives them but
+// freezes none (its violation pass is the critical path of most 2D iterations), and a quiet bit it
+// leaves on a listed anchor stays true (its targets are unchanged and final).
+template <int D, bool WG = false, bool FREEZE = !WG || D == 3>
 __device__ __forceinline__ void phase_vr(const FrontierView& B, const Dims& dm, int it, bool edit, int gtid,
                                          int gsize) {
     Slot& S = slot_of<WG>(B, it);
@@ -627,11 +760,24 @@ __device__ __forceinline__ void phase_vr(const FrontierView& B, const Dims& dm, 
     const int* vlist = B.vl[it & 1];
     const unsigned astamp_it = (unsigned)it;
     const unsigned* astamp = B.astamp[it & 1];
+    // the frozen violations (revived ones already removed by the gradient pass) count in this
+    // iteration as they are
+    const bool frozen = ld_relaxed(n_dead_of<WG>(B)) != 0;
+    if (gtid == 0 && frozen) {
+        for (int k = 0; k < 8; k++) {
+            const unsigned long long d = ld_relaxed(&B.ctl->dead_cnt[k]);
+            if (d) atomicAdd(&S.cnt[CNT_FP0 + k], d);
+        }
+        const unsigned long long dd = ld_relaxed(&B.ctl->dead_distinct);
+        if (dd) atomicAdd(&S.cnt[CNT_NREQ], dd);
+    }
+    int* n_frz = &S.n_frz;
     for (int base = 0; base < ntot; base += gsize) {
         if (wave_done(base, gtid, ntot)) break;
         const int i0 = base + gtid;
-        uint32_t m = 0;
+        uint32_t m = 0, old_quiet = 0;
         int a = 0;
+        bool listed = false;
         if (i0 < na) {
             a = it == 0 ? i0 : alist[i0];
             int x, y, z;
@@ -640,11 +786,27 @@ __device__ __forceinline__ void phase_vr(const FrontierView& B, const Dims& dm, 
             B.vmask[a] = m;
         } else if (i0 < ntot) {
             a = vlist[i0 - na];
-            if (astamp[a] != astamp_it) m = B.vmask[a];
+            if (astamp[a] != astamp_it) {
+                const uint32_t mv = B.vmask[a];
+                m = mv & VM_PLANES;
+                old_quiet = mv & VM_QUIET;
+                listed = true;
+            }
         }
-        const int idx = wave_append(m != 0, n_next);
-        if (m != 0) next[idx] = a;
-        anchor_requests<D, WG>(B, dm, a, m, it, edit, cnt, rc);
+        // a listed anchor (not affected since it was last examined, so its targets are the same)
+        // whose targets were all at their floor then is frozen after this pass
+        const bool frz = FREEZE && listed && m != 0 && old_quiet;
+        const int idx = wave_append(m != 0 && !frz, n_next);
+        if (m != 0 && !frz) next[idx] = a;
+        const int fi = wave_append(frz, n_frz);
+        if (frz) B.frz[fi] = a;
+        bool quiet = true;
+        anchor_requests<D, WG>(B, dm, a, m, it, edit, cnt, rc, quiet, frozen, FREEZE);
+        // the quiet bit is rewritten only when it changes (rarely)
+        if constexpr (FREEZE) {
+            const uint32_t qb = (m != 0 && quiet) ? VM_QUIET : 0u;
+            if ((i0 < na || (listed && !frz)) && qb != old_quiet) B.vmask[a] = m | qb;
+        }
     }
     // first differing cell of the f-branches, kept up to date for the separatrix step: every
     // branch at iteration 0 (first[] starts at INF32), afterwards the branches listed by the
@@ -930,10 +1092,14 @@ __global__ void k_fr_init(Ctl* c) {
     c->c_it = c->s_it = 0;
     c->residual = 0;
     c->ph[0] = c->ph[1] = c->ph[2] = 0;
+    for (int k = 0; k < 8; k++) c->dead_cnt[k] = 0;
+    c->dead_distinct = 0;
+    c->n_ftgt = 0;
+    c->n_dead = 0;
     for (int i = 0; i < 3; i++) {
         for (int k = 0; k < CNT_WORDS; k++) c->slot[i].cnt[k] = 0;
         c->slot[i].n_dv = c->slot[i].n_da = c->slot[i].n_vl = c->slot[i].n_db = 0;
-        c->slot[i].n_scan = c->slot[i].n_tc = 0;
+        c->slot[i].n_scan = c->slot[i].n_tc = c->slot[i].n_frz = 0;
     }
 }
 
@@ -1011,6 +1177,7 @@ __device__ __forceinline__ void run_job_wg(const FrontierView& B, int max_passes
         const int* src = reinterpret_cast<const int*>(c->slot);
         int* dst = reinterpret_cast<int*>(wg_slots);
         for (int k = tid; k < SLOT_WORDS; k += nt) dst[k] = src[k];
+        if (tid == 0) wg_n_dead = ld_relaxed(&c->n_dead);
     }
     __syncthreads();
     unsigned long long ph[3] = {0, 0, 0};
@@ -1075,10 +1242,9 @@ __device__ __forceinline__ void run_job_wg(const FrontierView& B, int max_passes
         tick(1);
         phase_vr<D, true>(B, dm, it, (long long)it != B.max_iters, tid, nt);
         __syncthreads();
-        if (B.tier >= 3) {
-            phase_bscan<D, true>(B, dm, it, tid, nt);
-            __syncthreads();
-        }
+        if constexpr (D == 3) freeze_pass<D, true>(B, dm, it, tid, nt);
+        if (B.tier >= 3) phase_bscan<D, true>(B, dm, it, tid, nt);
+        if (D == 3 || B.tier >= 3) __syncthreads();
         tick(2);
     }
     __syncthreads();
@@ -1086,6 +1252,7 @@ __device__ __forceinline__ void run_job_wg(const FrontierView& B, int max_passes
         const int* src = reinterpret_cast<const int*>(wg_slots);
         int* dst = reinterpret_cast<int*>(c->slot);
         for (int k = tid; k < SLOT_WORDS; k += nt) dst[k] = src[k];
+        if (tid == 0) c->n_dead = wg_n_dead;
     }
     if (tid == 0)
         for (int k = 0; k < 3; k++) c->ph[k] += ph[k];
@@ -1173,7 +1340,10 @@ template <int D>
 __global__ void __launch_bounds__(256) k_fr_bscan(FrontierBufs hb, Dims dm) {
     const FrontierView& B = view(hb);
     if (!running(B.ctl)) return;
-    phase_bscan<D>(B, dm, ld_relaxed(&B.ctl->it), blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+    const int it = ld_relaxed(&B.ctl->it);
+    const int gtid = blockIdx.x * blockDim.x + threadIdx.x, gsize = gridDim.x * blockDim.x;
+    freeze_pass<D>(B, dm, it, gtid, gsize);
+    phase_bscan<D>(B, dm, it, gtid, gsize);
 }
 
 template <int D>

@@ -93,13 +93,14 @@ struct JobWs {
     DevBuf lo, g0, g1, state, fpl, gpl, vmask, vl0, vl1, dvl0, dvl1, dal0, dal1, vstamp, astamp, astamp1, rstamp;
     DevBuf vpos, vstart, tsum, toff, ecell, bstamp, tcl, dbl, newmin, cand0, cand1, inlist;
     DevBuf ss_src, ss_q0, ss_q1, ss_stamp;
+    DevBuf fofs, ftgt, dreq, frz;
     MscBufs msc;
     std::vector<DevBuf*> all() {
         std::vector<DevBuf*> v = {&lo,     &g0,     &g1,      &state,  &fpl,   &gpl,   &vmask,  &vl0,
                                   &vl1,    &dvl0,   &dvl1,    &dal0,   &dal1,  &vstamp, &astamp, &astamp1,
                                   &rstamp, &vpos,   &vstart,  &tsum,   &toff,   &ecell, &bstamp, &tcl,
                                   &dbl,    &newmin, &cand0,   &cand1,  &inlist, &ss_src, &ss_q0,  &ss_q1,
-                                  &ss_stamp};
+                                  &ss_stamp, &fofs, &ftgt,  &dreq,    &frz};
         for (DevBuf* b : msc.all()) v.push_back(b);
         return v;
     }
@@ -240,6 +241,7 @@ dmt_status check_grid(dmt_context* c, const dmt_grid* gr, Dims& dm, int& D) {
     dm.nz = (int)gr->nz;
     dm.nxy = dm.nx * dm.ny;
     dm.n = (int)n;
+    set_divisors(dm);
     return DMT_OK;
 }
 
@@ -519,6 +521,13 @@ dmt_status job_frontier(dmt_context* c, Job& J, Ctl* ctl, hipStream_t st) {
     ENSURE(c, w.astamp, sizeof(unsigned) * n);
     ENSURE(c, w.astamp1, sizeof(unsigned) * n);
     ENSURE(c, w.rstamp, sizeof(unsigned) * n);
+    // frozen anchors: targets of up to 4 violations per vertex on average, then none freeze more
+    const int64_t ftgt_cap = std::max<int64_t>(4 * (int64_t)n, 1 << 16);
+    ENSURE(c, w.fofs, sizeof(int) * n);
+    ENSURE(c, w.ftgt, sizeof(int) * (size_t)ftgt_cap);
+    ENSURE(c, w.dreq, sizeof(unsigned) * n);
+    ENSURE(c, w.frz, sizeof(int) * n);
+    HIPCHK(c, hipMemsetAsync(w.dreq.p, 0, sizeof(unsigned) * n, st));
     HIPCHK(c, hipMemcpyAsync(w.g1.p, w.g0.p, sizeof(float) * n, hipMemcpyDeviceToDevice, st));
     HIPCHK(c, hipMemsetAsync(w.vstamp.p, 0, sizeof(unsigned) * n, st));
     HIPCHK(c, hipMemsetAsync(w.astamp.p, 0, sizeof(unsigned) * n, st));
@@ -551,6 +560,11 @@ dmt_status job_frontier(dmt_context* c, Job& J, Ctl* ctl, hipStream_t st) {
     B.astamp[0] = P<unsigned>(w.astamp);
     B.astamp[1] = P<unsigned>(w.astamp1);
     B.rstamp = P<unsigned>(w.rstamp);
+    B.fofs = P<int>(w.fofs);
+    B.ftgt = P<int>(w.ftgt);
+    B.dreq = P<unsigned>(w.dreq);
+    B.frz = P<int>(w.frz);
+    B.ftgt_cap = (int)ftgt_cap;
     B.log = nullptr;
     if (w.msc.valid) {
         MscBufs& m = w.msc;
@@ -681,7 +695,7 @@ dmt_status grid_iterations(dmt_context* c, const FrontierBufs& B, const Dims& dm
     for (int k = 0; k <= K; k++) {
         k_fr_grad<D><<<gfull, TPB, 0, st>>>(B, dm);
         k_fr_vr<D><<<gfull, TPB, 0, st>>>(B, dm);
-        if (B.tier >= 3) k_fr_bscan<D><<<gfull, TPB, 0, st>>>(B, dm);
+        k_fr_bscan<D><<<gfull, TPB, 0, st>>>(B, dm);
         if (k == K) break;
         if (B.tier >= 3) k_fr_sapply<D><<<gfull, TPB, 0, st>>>(B, dm);
         if (B.ss_on) k_fr_ss<<<1, 1024, 0, st>>>(B, dm);
@@ -894,10 +908,8 @@ dmt_status run_phases(dmt_context* c, Job& J, hipStream_t st) {
             ProfScope ps(c, DMT_PROF_LOOP, st, 0);
             k_fr_grad<D><<<gfull, TPB, 0, st>>>(J.B, J.dm);
             k_fr_vr<D><<<gfull, TPB, 0, st>>>(J.B, J.dm);
-            if (J.o.tier >= 3) {
-                k_fr_bscan<D><<<gfull, TPB, 0, st>>>(J.B, J.dm);
-                k_fr_sapply<D><<<gfull, TPB, 0, st>>>(J.B, J.dm);
-            }
+            k_fr_bscan<D><<<gfull, TPB, 0, st>>>(J.B, J.dm);
+            if (J.o.tier >= 3) k_fr_sapply<D><<<gfull, TPB, 0, st>>>(J.B, J.dm);
             if (J.B.ss_on) k_fr_ss<<<1, 1024, 0, st>>>(J.B, J.dm);
             k_fr_finish<<<1, 1, 0, st>>>(J.B);
             CHECK_LAUNCH(c);
@@ -1126,7 +1138,7 @@ int64_t workspace_estimate(int D, int64_t n, const dmt_options* o = nullptr) {
     // fields, state, f and g planes, frontier lists and stamps, separatrix branches (an upper
     // estimate of what the correction of one field allocates; the branches are data-dependent),
     // and the saddle-saddle walk's two level queues and edge stamps (7 edges per vertex, 4 B each)
-    int64_t est = (D == 2 ? 112 : 224) * n + (1 << 20);
+    int64_t est = (D == 2 ? 140 : 252) * n + (1 << 20);
     if (o && D == 3 && o->tier == 4 && (o->flags & DMT_F_SADDLE_SADDLE)) est += 84 * n;
     return est;
 }

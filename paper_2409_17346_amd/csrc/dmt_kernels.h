@@ -27,7 +27,29 @@ constexpr int INF32 = 0x7fffffff;
 
 struct Dims {
     int nx, ny, nz, nxy, n;
+    // division by nx and by nxy as a multiply-high, add and shift (set_divisors):
+    // floor(v / d) = (mulhi(v, m) + v) >> l for 0 <= v < 2^31
+    uint32_t mx, mxy;
+    int lx, lxy;
 };
+
+// Multiplier and shift of the exact unsigned division by d >= 1 (the round-up method for
+// division by invariant integers, Granlund and Montgomery 1994): l = ceil(log2 d),
+// m = floor(2^32 (2^l - d) / d) + 1.  mulhi(v, m) + v stays below 2^32 for v < 2^31.
+inline void div_magic(uint32_t d, uint32_t& m, int& l) {
+    l = 0;
+    while ((1ull << l) < d) l++;
+    m = (uint32_t)((((1ull << l) - d) << 32) / d + 1);
+}
+
+inline void set_divisors(Dims& d) {
+    div_magic((uint32_t)d.nx, d.mx, d.lx);
+    div_magic((uint32_t)d.nxy, d.mxy, d.lxy);
+}
+
+__device__ __forceinline__ int div_by(int v, uint32_t m, int l) {
+    return (int)((__umulhi((uint32_t)v, m) + (uint32_t)v) >> l);
+}
 
 // Counter block layout (one iteration): matches the public per-iteration log record.
 enum {
@@ -47,9 +69,9 @@ __device__ __forceinline__ int c27_lin(const Dims& d, int c) {
 }
 
 __device__ __forceinline__ void coords(const Dims& d, int v, int& x, int& y, int& z) {
-    z = v / d.nxy;
+    z = div_by(v, d.mxy, d.lxy);
     int r = v - z * d.nxy;
-    y = r / d.nx;
+    y = div_by(r, d.mx, d.lx);
     x = r - y * d.nx;
 }
 
