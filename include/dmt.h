@@ -382,8 +382,9 @@ dmt_status dmt_unpack_edits(dmt_context *ctx, const uint32_t *stream, int64_t st
 /* Kernel families timed by dmt_profile_*: */
 enum {
     DMT_PROF_GRADIENT = 0,  /* lower-star gradient pass, units = vertices */
-    DMT_PROF_CLASSIFY = 1,  /* critical-cell violation pass over every anchor, units = anchors */
-    DMT_PROF_APPLY = 2,     /* Equation 2 edit pass, units = vertices */
+    DMT_PROF_CLASSIFY = 1,  /* critical-cell classification over every anchor (iteration 0), units = anchors */
+    DMT_PROF_APPLY = 2,     /* Equation 2 edits: the dense form's pass (units = vertices), or the requests
+                               and edits of iteration 0's listed violations (units 0) */
     DMT_PROF_SSTEP = 3,     /* separatrix troublemaker pass, units = branch cells */
     DMT_PROF_SETUP = 4,     /* floors and validation, units = vertices */
     DMT_PROF_MSC = 5,       /* critical cells + separatrix branches of f, units = vertices */

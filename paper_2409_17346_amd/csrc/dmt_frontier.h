@@ -50,6 +50,7 @@ struct Ctl {
     unsigned long long dead_distinct;
     int n_ftgt;
     int n_dead;             // frozen anchors (in LDS while the resident loop runs)
+    int n_v0;               // violating anchors of iteration 0 (k_fr_classify0), listed in vl[0]
     Slot slot[3];
 };
 
@@ -753,7 +754,8 @@ __device__ __forceinline__ void phase_vr(const FrontierView& B, const Dims& dm, 
     int rc[2] = {0, 0};
     // One index space: the affected anchors (every anchor at iteration 0) get new masks; the
     // anchors listed by the previous iteration and not affected since keep theirs.
-    const int na = it == 0 ? dm.n : ld_relaxed(&S.n_da);
+    // iteration 0: only the violating anchors the classification pass listed (masks computed)
+    const int na = it == 0 ? ld_relaxed(&B.ctl->n_v0) : ld_relaxed(&S.n_da);
     const int nl = it == 0 ? 0 : ld_relaxed(&S.n_vl);
     const int ntot = na + nl;
     const int* alist = B.dal[it & 1];
@@ -778,8 +780,11 @@ __device__ __forceinline__ void phase_vr(const FrontierView& B, const Dims& dm, 
         uint32_t m = 0, old_quiet = 0;
         int a = 0;
         bool listed = false;
-        if (i0 < na) {
-            a = it == 0 ? i0 : alist[i0];
+        if (i0 < na && it == 0) {
+            a = B.vl[0][i0];
+            m = B.vmask[a];
+        } else if (i0 < na) {
+            a = alist[i0];
             int x, y, z;
             coords(dm, a, x, y, z);
             m = vmask_anchor<D>(dm, a, x, y, z, B.fpl, B.gpl, B.tier);
@@ -1096,6 +1101,7 @@ __global__ void k_fr_init(Ctl* c) {
     c->dead_distinct = 0;
     c->n_ftgt = 0;
     c->n_dead = 0;
+    c->n_v0 = 0;
     for (int i = 0; i < 3; i++) {
         for (int k = 0; k < CNT_WORDS; k++) c->slot[i].cnt[k] = 0;
         c->slot[i].n_dv = c->slot[i].n_da = c->slot[i].n_vl = c->slot[i].n_db = 0;
@@ -1325,6 +1331,30 @@ __global__ void __launch_bounds__(256) k_fr_grad(FrontierBufs hb, Dims dm) {
     const FrontierView& B = view(hb);
     if (!running(B.ctl)) return;
     phase_grad<D>(B, dm, ld_relaxed(&B.ctl->it), blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+}
+
+// Iteration 0's critical-cell classification as a streaming pass (a4): every anchor's violation
+// mask from its f and g codes in every plane (each plane a byte array, read once, coalesced) and
+// the list of violating anchors in vl[0], compacted by wave ballot and a block-wide prefix sum with
+// one atomic per block; the violation pass of iteration 0 then requests targets for the listed
+// anchors only.
+template <int D>
+__global__ void __launch_bounds__(256) k_fr_classify0(FrontierBufs hb, Dims dm) {
+    const FrontierView& B = view(hb);
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t m = 0;
+    if (a < dm.n) {
+        int x, y, z;
+        coords(dm, a, x, y, z);
+        m = vmask_anchor<D>(dm, a, x, y, z, B.fpl, B.gpl, B.tier);
+        B.vmask[a] = m;
+    }
+    __shared__ int base_sh;
+    int total;
+    const int off = block_exclusive_scan(m != 0 ? 1 : 0, total);
+    if (threadIdx.x == 0 && total) base_sh = atomicAdd(&B.ctl->n_v0, total);
+    __syncthreads();
+    if (m != 0) B.vl[0][base_sh + off] = a;
 }
 
 template <int D>
