@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SO = os.path.join(HERE, "libdmt.so")
 SOURCES = [os.path.join(HERE, "csrc", "dmt_host.hip")]
-DEPS = SOURCES + [os.path.join(HERE, "csrc", n) for n in ("dmt_kernels.h", "dmt_geom.h", "dmt_frontier.h", "dmt_verify.h")] + \
+DEPS = SOURCES + [os.path.join(HERE, "csrc", n) for n in ("dmt_kernels.h", "dmt_geom.h", "dmt_frontier.h", "dmt_verify.h", "dmt_codec.h")] + \
     [os.path.join(ROOT, "include", "dmt.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -8,8 +8,10 @@ no CPU fallback: if the library or a GPU is missing, calls raise.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import weakref
 from dataclasses import dataclass
 from typing import Dict, Optional, Tuple
 
@@ -173,6 +175,23 @@ def _stream(t: torch.Tensor):
     return VP(torch.cuda.current_stream(t.device).cuda_stream)
 
 
+# Contexts and servers still open when the interpreter exits are closed by an atexit hook, which
+# runs before the HIP runtime's own teardown; a destructor left to interpreter finalization could
+# otherwise free device memory after the runtime is gone.
+_live = weakref.WeakSet()
+
+
+def _close_all():
+    for o in sorted(list(_live), key=lambda o: not isinstance(o, Server)):   # servers first
+        try:
+            o.close()
+        except Exception:
+            pass
+
+
+atexit.register(_close_all)
+
+
 class Context:
     """Owns a dmt_context (device scratch + results of the last extraction / correction)."""
 
@@ -184,6 +203,7 @@ class Context:
         if st != DMT_OK:
             raise DmtError(st, "dmt_context_create failed")
         self.h = h
+        _live.add(self)
 
     def close(self):
         if getattr(self, "h", None):
@@ -559,6 +579,7 @@ class Server:
         if st != DMT_OK:
             raise DmtError(st, "dmt_server_create failed")
         self.h = h
+        _live.add(self)
         self._held = {}
         self._ctx = None   # context for reading lossless lists of finished jobs
 
