@@ -197,6 +197,40 @@ __device__ __forceinline__ bool wave_done(int base, int gtid, int n) {
 __shared__ Slot wg_slots[3];
 __shared__ int wg_n_dead;
 
+// Control words the resident loop keeps in LDS while it runs, like the slots (copied in when it
+// starts and back when it stops): the iteration, its outcome, the step counts and the
+// troublemaker candidate lists' selector and lengths.
+struct WgCtl {
+    int it, done, c_it, s_it, cand_sel, n_cand[2];
+};
+__shared__ WgCtl wg_ctl;
+
+template <bool WG = false>
+__device__ __forceinline__ int* cand_sel_of(const FrontierView& B) {
+    if constexpr (WG) return &wg_ctl.cand_sel;
+    else return &B.ctl->cand_sel;
+}
+
+template <bool WG = false>
+__device__ __forceinline__ int* n_cand_of(const FrontierView& B, int sel) {
+    if constexpr (WG) return &wg_ctl.n_cand[sel];
+    else return &B.ctl->n_cand[sel];
+}
+
+// Adds each thread's counts cnt[0, NC) to the slot counters cnt_out.  The resident loop's slots
+// are in LDS, where a lane adds its non-zero counts directly; the full-grid form sums the block
+// in LDS first and adds the block's totals to the slots in global memory.
+template <bool WG, int NC>
+__device__ __forceinline__ void add_counters(unsigned long long* cnt_out, const int* cnt) {
+    if constexpr (WG) {
+#pragma unroll
+        for (int k = 0; k < NC; k++)
+            if (cnt[k]) atomicAdd(&cnt_out[k], (unsigned long long)cnt[k]);
+    } else {
+        block_add_counters<NC>(cnt_out, cnt);
+    }
+}
+
 template <bool WG = false>
 __device__ __forceinline__ Slot& slot_of(const FrontierView& B, int it) {
     if constexpr (WG) return wg_slots[it % 3];
@@ -695,7 +729,7 @@ __device__ __forceinline__ void phase_bscan(const FrontierView& B, const Dims& d
     Slot& S = slot_of<WG>(B, it);
     const int n = ld_relaxed(&S.n_db);
     const int lane = __lane_id();
-    const int sel = ld_relaxed(&B.ctl->cand_sel);
+    const int sel = ld_relaxed(cand_sel_of<WG>(B));
     int scanned = 0;
     for (int i = gtid >> 6; i < n; i += gsize >> 6) {
         const int bb = B.dbl[i];
@@ -729,7 +763,7 @@ __device__ __forceinline__ void phase_bscan(const FrontierView& B, const Dims& d
             B.newmin[bb] = INF32;
             if (res != INF32 && !B.inlist[bb]) {
                 B.inlist[bb] = 1;
-                B.cand[sel][atomicAdd(&B.ctl->n_cand[sel], 1)] = bb;
+                B.cand[sel][atomicAdd(n_cand_of<WG>(B, sel), 1)] = bb;
             }
         }
     }
@@ -826,8 +860,8 @@ __device__ __forceinline__ void phase_vr(const FrontierView& B, const Dims& dm, 
             touched_cells<D, WG>(B, dm, it, gtid, gsize);
         }
     }
-    block_add_counters<8>(S.cnt + CNT_FP0, cnt);
-    block_add_counters<2>(S.cnt + CNT_NREQ, rc);
+    add_counters<WG, 8>(S.cnt + CNT_FP0, cnt);
+    add_counters<WG, 2>(S.cnt + CNT_NREQ, rc);
 }
 
 // Troublemaker targets (apex of the f-pair of each branch's first differing cell), edited at
@@ -840,8 +874,8 @@ __device__ __forceinline__ void phase_sapply(const FrontierView& B, const Dims& 
     int rc[2] = {0, 0};
     // the candidate list: members whose first differing cell is unset leave it, the others are
     // kept in the other buffer (the decision of this iteration makes it current)
-    const int sel = ld_relaxed(&B.ctl->cand_sel);
-    const int nb = ld_relaxed(&B.ctl->n_cand[sel]);
+    const int sel = ld_relaxed(cand_sel_of<WG>(B));
+    const int nb = ld_relaxed(n_cand_of<WG>(B, sel));
     const int* cl = B.cand[sel];
     int* keep = B.cand[sel ^ 1];
     for (int base = 0; base < nb; base += gsize) {
@@ -901,12 +935,12 @@ __device__ __forceinline__ void phase_sapply(const FrontierView& B, const Dims& 
                 }
             }
         }
-        const int idx = wave_append(kept, &B.ctl->n_cand[sel ^ 1]);
+        const int idx = wave_append(kept, n_cand_of<WG>(B, sel ^ 1));
         if (kept) keep[idx] = bb;
         request_apply<D, WG>(B, dm, target, it, edit, rc);
     }
-    block_add_counters<2>(slot_of<WG>(B, it).cnt + CNT_TM_DESC, c);
-    block_add_counters<2>(slot_of<WG>(B, it).cnt + CNT_NREQ, rc);
+    add_counters<WG, 2>(slot_of<WG>(B, it).cnt + CNT_TM_DESC, c);
+    add_counters<WG, 2>(slot_of<WG>(B, it).cnt + CNT_NREQ, rc);
 }
 
 // ---- saddle-saddle connectors (3D) --------------------------------------------------------
@@ -1003,8 +1037,8 @@ __device__ __forceinline__ void phase_ss(const FrontierView& B, const Dims& dm, 
     int rc[2] = {0, 0};
     int c = ss_walk(B.fpl, B.gpl, dm, B.ss_src, B.n_ss_src, B.ss_q[0], B.ss_q[1], B.ss_stamp, (unsigned)it + 1u,
                     tid, nt, [&](int target) { request_apply<3, WG>(B, dm, target, it, edit, rc); });
-    block_add_counters<1>(slot_of<WG>(B, it).cnt + CNT_TM_SS, &c);
-    block_add_counters<2>(slot_of<WG>(B, it).cnt + CNT_NREQ, rc);
+    add_counters<WG, 1>(slot_of<WG>(B, it).cnt + CNT_TM_SS, &c);
+    add_counters<WG, 2>(slot_of<WG>(B, it).cnt + CNT_NREQ, rc);
 }
 
 // Edges of f's 2-saddles (critical triangles, ids a * 12 + type): three per triangle into src.
@@ -1118,11 +1152,12 @@ __device__ __forceinline__ void cand_flip(Ctl* c) {
     c->cand_sel = sel ^ 1;
 }
 
-// iteration_state and record_iteration for a whole wave (wave 0 of the workgroup): lane k
-// loads counter k, so the loads are issued together, and writes log word k.
-template <bool WG>
-__device__ __forceinline__ int wave_decide(const FrontierView& B, int it, int lane) {
-    const Slot& S = slot_of<WG>(B, it);
+// iteration_state and record_iteration of the resident loop for a whole wave (wave 0 of the
+// workgroup): lane k loads counter k, so the loads are issued together, and returns log word k in
+// *rec (the caller stores the record while the next iteration's gradient pass runs).  The step
+// counts and the candidate-list selector are the LDS copies (wg_ctl).
+__device__ __forceinline__ int wave_decide(const FrontierView& B, int it, int lane, long long* rec) {
+    const Slot& S = wg_slots[it % 3];
     const unsigned long long v = lane < CNT_WORDS ? ld_relaxed(&S.cnt[lane]) : 0ull;
     const unsigned long long cv = (lane >= CNT_FP0 && lane < CNT_FP0 + 8) ? v : 0ull;
     const unsigned long long tv = (lane == CNT_TM_DESC || lane == CNT_TM_ASC || lane == CNT_TM_SS) ? v : 0ull;
@@ -1139,26 +1174,30 @@ __device__ __forceinline__ int wave_decide(const FrontierView& B, int it, int la
     if (viol == 0) st = 1;
     else if ((long long)it == B.max_iters) st = 2;
     else if (changed == 0) st = 3;
-    Ctl* c = B.ctl;
-    if (st == 0 && B.log) {
-        long long* rec = B.log + (size_t)it * DMT_LOG_WORDS;
-        if (lane == 0) rec[0] = ct ? 1 : 2;
-        else if (lane < CNT_WORDS && lane <= CNT_CHANGED) rec[lane] = (long long)v;
-        else if (lane == 13) rec[13] = ld_relaxed(&S.n_dv);
-        else if (lane == 14) rec[14] = ld_relaxed(&S.n_da);
-        else if (lane == 15) rec[15] = ld_relaxed(&S.n_vl);
-        else if (lane == 16) rec[16] = ld_relaxed(&S.n_db);
-        else if (lane == 17) rec[17] = ld_relaxed(&S.n_scan);
-        else if (lane == 18) rec[18] = ld_relaxed(&S.n_tc);
-        else if (lane == 20) rec[20] = (long long)tm_ss;
-    }
+    long long r = 0;
+    if (lane == 0) r = ct ? 1 : 2;
+    else if (lane <= CNT_CHANGED) r = (long long)v;
+    else if (lane == 13) r = ld_relaxed(&S.n_dv);
+    else if (lane == 14) r = ld_relaxed(&S.n_da);
+    else if (lane == 15) r = ld_relaxed(&S.n_vl);
+    else if (lane == 16) r = ld_relaxed(&S.n_db);
+    else if (lane == 17) r = ld_relaxed(&S.n_scan);
+    else if (lane == 18) r = ld_relaxed(&S.n_tc);
+    else if (lane == 20) r = (long long)tm_ss;
+    *rec = r;
     if (lane == 0) {
-        if (st == 2 || st == 3) c->residual = (long long)viol;
+        if (st == 2 || st == 3) B.ctl->residual = (long long)viol;
         if (st == 0) {
-            if (ct) c->c_it++;
-            else c->s_it++;
+            if (ct) wg_ctl.c_it++;
+            else wg_ctl.s_it++;
         }
-        if (ct == 0 && B.tier >= 3) cand_flip(c);
+        if (ct == 0 && B.tier >= 3) {   // the list the troublemaker pass kept becomes current
+            const int sel = wg_ctl.cand_sel;
+            wg_ctl.n_cand[sel] = 0;
+            wg_ctl.cand_sel = sel ^ 1;
+        }
+        wg_ctl.it = st ? it : it + 1;
+        wg_ctl.done = st;
     }
     return st;
 }
@@ -1170,6 +1209,8 @@ __device__ __forceinline__ int wave_decide(const FrontierView& B, int it, int la
 // an iteration with more than big affected and listed anchors (ctl->it that iteration, whose
 // passes have not started), ctl->paused = 2 before a troublemaker pass over more than big
 // candidates (ctl->it the iteration it belongs to); the host runs those as full-grid launches.
+// An iteration with critical-cell violations is decided as soon as its passes end; one without
+// runs its troublemaker pass first.
 template <int D>
 __device__ __forceinline__ void run_job_wg(const FrontierView& B, int max_passes, int big) {
     const Dims dm = B.dm;
@@ -1183,33 +1224,72 @@ __device__ __forceinline__ void run_job_wg(const FrontierView& B, int max_passes
         const int* src = reinterpret_cast<const int*>(c->slot);
         int* dst = reinterpret_cast<int*>(wg_slots);
         for (int k = tid; k < SLOT_WORDS; k += nt) dst[k] = src[k];
-        if (tid == 0) wg_n_dead = ld_relaxed(&c->n_dead);
+        if (tid == 0) {
+            wg_n_dead = ld_relaxed(&c->n_dead);
+            wg_ctl.it = it;
+            wg_ctl.done = 0;
+            wg_ctl.c_it = c->c_it;
+            wg_ctl.s_it = c->s_it;
+            wg_ctl.cand_sel = c->cand_sel;
+            wg_ctl.n_cand[0] = c->n_cand[0];
+            wg_ctl.n_cand[1] = c->n_cand[1];
+        }
     }
     __syncthreads();
     unsigned long long ph[3] = {0, 0, 0};
     unsigned long long t = tid == 0 ? wall_clock64() : 0;
-    unsigned long long t_it = t;   // start of the current iteration's gradient pass
+    unsigned long long t_it = tid < 64 ? wall_clock64() : 0;   // start of the current iteration's gradient pass
     auto tick = [&](int k) {
         if (tid == 0) { const unsigned long long t1 = wall_clock64(); ph[k] += t1 - t; t = t1; }
     };
     // decisions are taken by wave 0 and shared through LDS; each variable is written again only
     // after several more workgroup barriers, when every wave has read it
     __shared__ int sstep_sh, state_sh;
+    // wave 0 holds the log record of the last decided iteration (lane k: word k) until it is stored
+    long long rec = 0;
+    int rec_it = -1;
+    auto flush = [&]() {
+        if (tid < 64 && rec_it >= 0) {
+            if (tid < DMT_LOG_WORDS) B.log[(size_t)rec_it * DMT_LOG_WORDS + tid] = rec;
+            rec_it = -1;
+        }
+    };
+    // wave 0: decides iteration it (state_sh: 0 go on, 1-3 done, 4 pause before the next one)
+    auto decide = [&]() {
+        const int st = wave_decide(B, it, tid, &rec);
+        if (tid == 19) rec = (long long)(wall_clock64() - t_it);
+        int act = st;
+        // a large next iteration is left to full-grid launches: pause before its gradient pass
+        if (st == 0 && big > 0) {
+            const Slot& N = wg_slots[(it + 1) % 3];
+            if (ld_relaxed(&N.n_da) + ld_relaxed(&N.n_vl) > big) {
+                if (tid == 0) c->paused = 1;
+                act = 4;
+            }
+        }
+        if (st == 0 && B.log) rec_it = it;
+        if (tid == 0) state_sh = act;
+    };
     for (int pass = 0; pass < max_passes; pass++) {
         if (B.log && it >= B.log_cap) break;
         if (tid < 64) {
-            const bool s_step = B.tier >= 3 && c_total(slot_of<true>(B, it)) == 0;
-            int act = s_step;
-            // a troublemaker pass over more than `big` candidates is left to the grid too
-            if (s_step && big > 0 && ld_relaxed(&c->n_cand[ld_relaxed(&c->cand_sel)]) > big) {
+            const bool s_step = B.tier >= 3 && c_total(wg_slots[it % 3]) == 0;
+            int act = 0;
+            if (!s_step) {
+                decide();
+            } else if (big > 0 && ld_relaxed(&wg_ctl.n_cand[wg_ctl.cand_sel]) > big) {
+                // a troublemaker pass over more than `big` candidates is left to the grid too
                 if (tid == 0) c->paused = 2;
                 act = 2;
+            } else {
+                act = 1;
             }
             if (tid == 0) sstep_sh = act;
         }
         __syncthreads();
-        if (sstep_sh == 2) break;
-        if (sstep_sh) {
+        const int ss = sstep_sh;
+        if (ss == 2) break;
+        if (ss) {
             phase_sapply<D, true>(B, dm, it, (long long)it != B.max_iters, tid, nt);
             __syncthreads();
             if constexpr (D == 3) {
@@ -1218,31 +1298,15 @@ __device__ __forceinline__ void run_job_wg(const FrontierView& B, int max_passes
                     __syncthreads();
                 }
             }
+            if (tid < 64) decide();
+            __syncthreads();
         }
-        if (tid < 64) {
-            const int st = wave_decide<true>(B, it, tid);
-            if (tid == 0) {
-                if (B.log && st == 0) B.log[(size_t)it * DMT_LOG_WORDS + 19] = (long long)(wall_clock64() - t_it);
-                c->it = st ? it : it + 1;
-                c->done = st;
-                int act = st;
-                // a large next iteration is left to full-grid launches: pause before its gradient pass
-                if (st == 0 && big > 0) {
-                    const Slot& N = slot_of<true>(B, it + 1);
-                    if (ld_relaxed(&N.n_da) + ld_relaxed(&N.n_vl) > big) {
-                        c->paused = 1;
-                        act = 4;
-                    }
-                }
-                state_sh = act;
-            }
-        }
-        __syncthreads();
         const int st = state_sh;
         tick(0);
         if (st) break;
         it++;
-        if (tid == 0) t_it = wall_clock64();
+        if (tid < 64) t_it = wall_clock64();
+        flush();
         phase_grad<D, true>(B, dm, it, tid, nt);
         __syncthreads();
         tick(1);
@@ -1253,15 +1317,24 @@ __device__ __forceinline__ void run_job_wg(const FrontierView& B, int max_passes
         if (D == 3 || B.tier >= 3) __syncthreads();
         tick(2);
     }
+    flush();
     __syncthreads();
     {
         const int* src = reinterpret_cast<const int*>(wg_slots);
         int* dst = reinterpret_cast<int*>(c->slot);
         for (int k = tid; k < SLOT_WORDS; k += nt) dst[k] = src[k];
-        if (tid == 0) c->n_dead = wg_n_dead;
+        if (tid == 0) {
+            c->n_dead = wg_n_dead;
+            c->it = wg_ctl.it;
+            c->done = wg_ctl.done;
+            c->c_it = wg_ctl.c_it;
+            c->s_it = wg_ctl.s_it;
+            c->cand_sel = wg_ctl.cand_sel;
+            c->n_cand[0] = wg_ctl.n_cand[0];
+            c->n_cand[1] = wg_ctl.n_cand[1];
+            for (int k = 0; k < 3; k++) c->ph[k] += ph[k];
+        }
     }
-    if (tid == 0)
-        for (int k = 0; k < 3; k++) c->ph[k] += ph[k];
     __syncthreads();
 }
 
