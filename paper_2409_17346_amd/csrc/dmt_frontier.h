@@ -662,11 +662,14 @@ __device__ __forceinline__ void phase_grad(const FrontierView& B, const Dims& dm
         int e0 = 0, e1 = 0;
         if (i < n) {
             const int t = list[i];
+            // the vertex's branch-cell range is loaded with its neighbourhood, before the code
+            // stores, so a changed vertex does not wait for it afterwards
+            const int s0 = track ? B.vstart[t] : 0, s1 = track ? B.vstart[t + 1] : 0;
             const bool ch = grad_vertex<D, true>(t, gcur, B.gpl, dm);
             gnext[t] = gcur[t];
             if (track && ch) {
-                e0 = B.vstart[t];
-                e1 = B.vstart[t + 1];
+                e0 = s0;
+                e1 = s1;
             }
         }
         if (track) {
@@ -1156,19 +1159,23 @@ __device__ __forceinline__ void cand_flip(Ctl* c) {
 // workgroup): lane k loads counter k, so the loads are issued together, and returns log word k in
 // *rec (the caller stores the record while the next iteration's gradient pass runs).  The step
 // counts and the candidate-list selector are the LDS copies (wg_ctl).
-__device__ __forceinline__ int wave_decide(const FrontierView& B, int it, int lane, long long* rec) {
-    const Slot& S = wg_slots[it % 3];
-    const unsigned long long v = lane < CNT_WORDS ? ld_relaxed(&S.cnt[lane]) : 0ull;
-    const unsigned long long cv = (lane >= CNT_FP0 && lane < CNT_FP0 + 8) ? v : 0ull;
-    const unsigned long long tv = (lane == CNT_TM_DESC || lane == CNT_TM_ASC || lane == CNT_TM_SS) ? v : 0ull;
-    unsigned long long ct = cv, tt = tv;
+__device__ __forceinline__ unsigned long long c_total_wg(const Slot& S) {
+    unsigned long long t = 0;
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        ct += __shfl_xor(ct, o, 64);
-        tt += __shfl_xor(tt, o, 64);
-    }
-    const unsigned long long changed = __shfl(v, CNT_CHANGED, 64);
-    const unsigned long long tm_ss = __shfl(v, CNT_TM_SS, 64);
+    for (int k = CNT_FP0; k < CNT_FP0 + 8; k++) t += S.cnt[k];
+    return t;
+}
+
+// ct: the iteration's critical-cell violations (c_total_wg of its slot).  Every lane reads the
+// counters it needs from LDS itself (the slot is final: the passes that fill it are behind a
+// barrier).
+__device__ __forceinline__ int wave_decide(const FrontierView& B, int it, int lane, unsigned long long ct,
+                                           long long* rec) {
+    const Slot& S = wg_slots[it % 3];
+    const unsigned long long v = lane < CNT_WORDS ? S.cnt[lane] : 0ull;
+    const unsigned long long tm_ss = S.cnt[CNT_TM_SS];
+    const unsigned long long tt = S.cnt[CNT_TM_DESC] + S.cnt[CNT_TM_ASC] + tm_ss;
+    const unsigned long long changed = S.cnt[CNT_CHANGED];
     const unsigned long long viol = ct ? ct : (B.tier >= 3 ? tt : 0ull);
     int st = 0;
     if (viol == 0) st = 1;
@@ -1177,12 +1184,12 @@ __device__ __forceinline__ int wave_decide(const FrontierView& B, int it, int la
     long long r = 0;
     if (lane == 0) r = ct ? 1 : 2;
     else if (lane <= CNT_CHANGED) r = (long long)v;
-    else if (lane == 13) r = ld_relaxed(&S.n_dv);
-    else if (lane == 14) r = ld_relaxed(&S.n_da);
-    else if (lane == 15) r = ld_relaxed(&S.n_vl);
-    else if (lane == 16) r = ld_relaxed(&S.n_db);
-    else if (lane == 17) r = ld_relaxed(&S.n_scan);
-    else if (lane == 18) r = ld_relaxed(&S.n_tc);
+    else if (lane == 13) r = S.n_dv;
+    else if (lane == 14) r = S.n_da;
+    else if (lane == 15) r = S.n_vl;
+    else if (lane == 16) r = S.n_db;
+    else if (lane == 17) r = S.n_scan;
+    else if (lane == 18) r = S.n_tc;
     else if (lane == 20) r = (long long)tm_ss;
     *rec = r;
     if (lane == 0) {
@@ -1255,14 +1262,14 @@ __device__ __forceinline__ void run_job_wg(const FrontierView& B, int max_passes
         }
     };
     // wave 0: decides iteration it (state_sh: 0 go on, 1-3 done, 4 pause before the next one)
-    auto decide = [&]() {
-        const int st = wave_decide(B, it, tid, &rec);
+    auto decide = [&](unsigned long long ct) {
+        const int st = wave_decide(B, it, tid, ct, &rec);
         if (tid == 19) rec = (long long)(wall_clock64() - t_it);
         int act = st;
         // a large next iteration is left to full-grid launches: pause before its gradient pass
         if (st == 0 && big > 0) {
             const Slot& N = wg_slots[(it + 1) % 3];
-            if (ld_relaxed(&N.n_da) + ld_relaxed(&N.n_vl) > big) {
+            if (N.n_da + N.n_vl > big) {
                 if (tid == 0) c->paused = 1;
                 act = 4;
             }
@@ -1273,11 +1280,12 @@ __device__ __forceinline__ void run_job_wg(const FrontierView& B, int max_passes
     for (int pass = 0; pass < max_passes; pass++) {
         if (B.log && it >= B.log_cap) break;
         if (tid < 64) {
-            const bool s_step = B.tier >= 3 && c_total(wg_slots[it % 3]) == 0;
+            const unsigned long long ct = c_total_wg(wg_slots[it % 3]);
+            const bool s_step = B.tier >= 3 && ct == 0;
             int act = 0;
             if (!s_step) {
-                decide();
-            } else if (big > 0 && ld_relaxed(&wg_ctl.n_cand[wg_ctl.cand_sel]) > big) {
+                decide(ct);
+            } else if (big > 0 && wg_ctl.n_cand[wg_ctl.cand_sel] > big) {
                 // a troublemaker pass over more than `big` candidates is left to the grid too
                 if (tid == 0) c->paused = 2;
                 act = 2;
@@ -1298,7 +1306,7 @@ __device__ __forceinline__ void run_job_wg(const FrontierView& B, int max_passes
                     __syncthreads();
                 }
             }
-            if (tid < 64) decide();
+            if (tid < 64) decide(0ull);
             __syncthreads();
         }
         const int st = state_sh;
