@@ -423,16 +423,28 @@ constexpr uint32_t VM_DEAD = 1u << 31;
 // Every plane's codes are loaded unconditionally (plane P of anchor a is in bounds for every
 // anchor), so all loads are in flight together; planes whose cell does not exist, or that the
 // tier ignores, are masked afterwards.
+// With fpk (2D), the anchor's f codes are also returned packed (plane P in byte P) with bit 63
+// set, so its targets need not load them again.
 template <int D>
 __device__ __forceinline__ uint32_t vmask_anchor(const Dims& dm, int a, int x, int y, int z,
                                                  const uint8_t* __restrict__ fpl, const uint8_t* __restrict__ gpl,
-                                                 int tier) {
+                                                 int tier, uint64_t* fpk = nullptr) {
     uint8_t fc[Geom<D>::NB], gc[Geom<D>::NB];
     static_for<0, Geom<D>::NB>([&](auto pc) {
         constexpr int P = decltype(pc)::value;
         fc[P] = fpl[(size_t)P * dm.n + a];
         gc[P] = gpl[(size_t)P * dm.n + a];
     });
+    if constexpr (D == 2) {
+        if (fpk) {
+            uint64_t k = 1ull << 63;
+            static_for<0, Geom<D>::NB>([&](auto pc) {
+                constexpr int P = decltype(pc)::value;
+                k |= (uint64_t)fc[P] << (8 * P);
+            });
+            *fpk = k;
+        }
+    }
     uint32_t m = 0;
     static_for<0, Geom<D>::NB>([&](auto pc) {
         constexpr int P = decltype(pc)::value;
@@ -503,9 +515,9 @@ __device__ __forceinline__ int plane_target_dyn(int p, const FrontierView& B, co
 // the per-plane code.
 template <int D>
 __device__ __forceinline__ int plane_target_any(int p, const FrontierView& B, const Dims& dm, int a, const float* gcur,
-                                                int* cnt) {
+                                                int* cnt, uint64_t fpk = 0) {
     constexpr auto& g = G<D>::g;
-    const uint8_t fc = B.fpl[(size_t)p * dm.n + a];
+    const uint8_t fc = (fpk >> 63) ? (uint8_t)(fpk >> (8 * p)) : B.fpl[(size_t)p * dm.n + a];
     if (fc != CODE_CRIT) {
         int dim = (p >= g.base[1]) + (p >= g.base[2]);
         if constexpr (D == 3) dim += (p >= g.base[3]);
@@ -524,7 +536,7 @@ __device__ __forceinline__ int plane_target_any(int p, const FrontierView& B, co
 template <int D, bool WG = false>
 __device__ __forceinline__ void anchor_requests(const FrontierView& B, const Dims& dm, int a, uint32_t m, int it,
                                                 bool edit, int* cnt, int* rc, bool& quiet, bool frozen,
-                                                bool track_quiet) {
+                                                bool track_quiet, uint64_t fpk = 0) {
     const float* gcur = B.gb[it & 1];
     for (;;) {
         if (__ballot(m != 0) == 0) break;
@@ -532,7 +544,7 @@ __device__ __forceinline__ void anchor_requests(const FrontierView& B, const Dim
         if (m != 0) {
             const int p = __ffs(m) - 1;
             m &= m - 1u;
-            target = plane_target_any<D>(p, B, dm, a, gcur, cnt);
+            target = plane_target_any<D>(p, B, dm, a, gcur, cnt, fpk);
         }
         request_apply<D, WG>(B, dm, target, it, edit, rc, track_quiet ? &quiet : nullptr, frozen);
     }
@@ -815,6 +827,7 @@ __device__ __forceinline__ void phase_vr(const FrontierView& B, const Dims& dm, 
         if (wave_done(base, gtid, ntot)) break;
         const int i0 = base + gtid;
         uint32_t m = 0, old_quiet = 0;
+        uint64_t fpk = 0;   // the anchor's f codes, when loaded here (2D)
         int a = 0;
         bool listed = false;
         if (i0 < na && it == 0) {
@@ -824,7 +837,7 @@ __device__ __forceinline__ void phase_vr(const FrontierView& B, const Dims& dm, 
             a = alist[i0];
             int x, y, z;
             coords(dm, a, x, y, z);
-            m = vmask_anchor<D>(dm, a, x, y, z, B.fpl, B.gpl, B.tier);
+            m = vmask_anchor<D>(dm, a, x, y, z, B.fpl, B.gpl, B.tier, &fpk);
             B.vmask[a] = m;
         } else if (i0 < ntot) {
             a = vlist[i0 - na];
@@ -843,7 +856,7 @@ __device__ __forceinline__ void phase_vr(const FrontierView& B, const Dims& dm, 
         const int fi = wave_append(frz, n_frz);
         if (frz) B.frz[fi] = a;
         bool quiet = true;
-        anchor_requests<D, WG>(B, dm, a, m, it, edit, cnt, rc, quiet, frozen, FREEZE);
+        anchor_requests<D, WG>(B, dm, a, m, it, edit, cnt, rc, quiet, frozen, FREEZE, fpk);
         // the quiet bit is rewritten only when it changes (rarely)
         if constexpr (FREEZE) {
             const uint32_t qb = (m != 0 && quiet) ? VM_QUIET : 0u;
