@@ -219,7 +219,7 @@ dmt_status dmt_correct(dmt_context *ctx, const dmt_grid *grid, const float *f, c
  * context as for dmt_correct; dmt_lossless_edits reports no entries after this call, and kernel
  * timing (dmt_profile_enable) is not recorded for it.
  * Limits: DMT_E_NOMEM, before any work, when dmt_workspace_bytes of the grid exceeds
- * DMT_NOALLOC_SCRATCH_BYTES (about 0.95 M vertices in 2D, 0.53 M in 3D), or during the call if a
+ * DMT_NOALLOC_SCRATCH_BYTES (about 0.92 M vertices in 2D, 0.50 M in 3D), or during the call if a
  * field's separatrices need more scratch than is left (outputs then undefined).
  * Concurrency: all calls on one GPU share its scratch array, which keeps the last call's
  * contents (each call initialises what it reads).  Calls that overlap in time on one GPU, from

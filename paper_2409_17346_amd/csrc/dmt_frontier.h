@@ -432,8 +432,8 @@ __device__ __forceinline__ uint32_t vmask_anchor(const Dims& dm, int a, int x, i
     uint8_t fc[Geom<D>::NB], gc[Geom<D>::NB];
     static_for<0, Geom<D>::NB>([&](auto pc) {
         constexpr int P = decltype(pc)::value;
-        fc[P] = fpl[(size_t)P * dm.n + a];
-        gc[P] = gpl[(size_t)P * dm.n + a];
+        fc[P] = fpl[pidx<D>(P, a)];
+        gc[P] = gpl[pidx<D>(P, a)];
     });
     if constexpr (D == 2) {
         if (fpk) {
@@ -461,8 +461,8 @@ template <int D, int P>
 __device__ __forceinline__ int plane_target(const FrontierView& B, const Dims& dm, int a, const float* gcur, int* cnt) {
     constexpr auto& g = G<D>::g;
     constexpr int dim = g.bdim[P];
-    const uint8_t fc = B.fpl[(size_t)P * dm.n + a];
-    const uint8_t gc = B.gpl[(size_t)P * dm.n + a];
+    const uint8_t fc = B.fpl[pidx<D>(P, a)];
+    const uint8_t gc = B.gpl[pidx<D>(P, a)];
     if (fc != CODE_CRIT) {
         cnt[2 * dim]++;
         return a + c27_lin(dm, fc & 63);
@@ -494,7 +494,7 @@ __device__ __forceinline__ int plane_target(const FrontierView& B, const Dims& d
                 fp = G<D>::g.facet_plane[P][k];
             }
         });
-        best = fa + c27_lin(dm, B.fpl[(size_t)fp * dm.n + fa] & 63);
+        best = fa + c27_lin(dm, B.fpl[pidx<D>(fp, fa)] & 63);
     }
     cnt[2 * dim + 1]++;
     return best;
@@ -517,7 +517,7 @@ template <int D>
 __device__ __forceinline__ int plane_target_any(int p, const FrontierView& B, const Dims& dm, int a, const float* gcur,
                                                 int* cnt, uint64_t fpk = 0) {
     constexpr auto& g = G<D>::g;
-    const uint8_t fc = (fpk >> 63) ? (uint8_t)(fpk >> (8 * p)) : B.fpl[(size_t)p * dm.n + a];
+    const uint8_t fc = (fpk >> 63) ? (uint8_t)(fpk >> (8 * p)) : B.fpl[pidx<D>(p, a)];
     if (fc != CODE_CRIT) {
         int dim = (p >= g.base[1]) + (p >= g.base[2]);
         if constexpr (D == 3) dim += (p >= g.base[3]);
@@ -593,7 +593,7 @@ __device__ __forceinline__ void revive_pass(const FrontierView& B, const Dims& d
             const int p = __ffs(m) - 1;
             m &= m - 1u;
             const int d = plane_dim<D>(p);
-            dc[2 * d + (B.fpl[(size_t)p * dm.n + a] == CODE_CRIT ? 1 : 0)]++;
+            dc[2 * d + (B.fpl[pidx<D>(p, a)] == CODE_CRIT ? 1 : 0)]++;
             if (atomicSub(&B.dreq[B.ftgt[o + k]], 1u) == 1u) dd++;
         }
     }
@@ -698,12 +698,12 @@ __device__ __forceinline__ bool branch_cell_differs(const FrontierView& B, const
     constexpr auto& g = G<D>::g;
     if (!asc) {
         const int v = B.dcell[k];
-        return B.fpl[v] != B.gpl[v];
+        return B.fpl[pidx<D>(0, v)] != B.gpl[pidx<D>(0, v)];
     }
     const int T = B.acell[k];
     const int a = T / g.ntypes[D];
     const int tp = T - a * g.ntypes[D] + g.base[D];
-    const size_t o = (size_t)tp * dm.n + a;
+    const size_t o = pidx<D>(tp, a);
     return B.fpl[o] != B.gpl[o];
 }
 
@@ -919,7 +919,7 @@ __device__ __forceinline__ void phase_sapply(const FrontierView& B, const Dims& 
                     if (!asc) {
                         int v = cells[k];
                         for (int step = 0; step < dm.n; step++) {
-                            const uint8_t cc = B.gpl[v];
+                            const uint8_t cc = B.gpl[pidx<D>(0, v)];
                             if (cc == CODE_CRIT) break;
                             v += c27_lin(dm, cc & 63);
                         }
@@ -940,12 +940,12 @@ __device__ __forceinline__ void phase_sapply(const FrontierView& B, const Dims& 
                 if (ok) {
                     if (!asc) {
                         const int v = cells[k];
-                        target = v + c27_lin(dm, B.fpl[v] & 63);
+                        target = v + c27_lin(dm, B.fpl[pidx<D>(0, v)] & 63);
                     } else {
                         const int T = cells[k];
                         const int a = T / g.ntypes[D];
                         const int tp = T - a * g.ntypes[D] + g.base[D];
-                        target = a + c27_lin(dm, B.fpl[(size_t)tp * dm.n + a] & 63);
+                        target = a + c27_lin(dm, B.fpl[pidx<D>(tp, a)] & 63);
                     }
                     c[asc ? 1 : 0]++;
                 }
@@ -1019,7 +1019,7 @@ __device__ __forceinline__ int ss_walk(const uint8_t* fpl, const uint8_t* gpl, c
                 const int e = q[cur][i];
                 const int c = e / n + 1;            // the edge's direction bits = its code plane
                 const int a = e - (c - 1) * n;
-                const uint8_t fc = fpl[(size_t)c * n + a], gc = gpl[(size_t)c * n + a];
+                const uint8_t fc = fpl[pidx<3>(c, a)], gc = gpl[pidx<3>(c, a)];
                 if (fc != gc) {
                     if (fc != CODE_CRIT) {
                         target = a + c27_lin(dm, fc & 63);

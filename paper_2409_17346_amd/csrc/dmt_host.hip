@@ -256,7 +256,8 @@ dmt_status check_options(dmt_context* c, const dmt_options* o, float xi) {
     return DMT_OK;
 }
 
-int nplanes(int D) { return D == 2 ? Geom<2>::NB : Geom<3>::NB; }
+// bytes of code planes per vertex (anchor-major, padded)
+int plane_bytes(int D) { return D == 2 ? plane_stride<2>() : plane_stride<3>(); }
 int ntypes(int D, int d) { return D == 2 ? G<2>::g.ntypes[d] : G<3>::g.ntypes[d]; }
 
 hipEvent_t next_event(dmt_context* c) {
@@ -463,8 +464,8 @@ dmt_status job_setup(dmt_context* c, Job& J, unsigned* flag, hipStream_t st) {
     ENSURE(c, w.lo, sizeof(float) * n);
     ENSURE(c, w.g0, sizeof(float) * n);
     ENSURE(c, w.state, n);
-    ENSURE(c, w.fpl, (size_t)Geom<D>::NB * n);
-    ENSURE(c, w.gpl, (size_t)Geom<D>::NB * n);
+    ENSURE(c, w.fpl, (size_t)plane_stride<D>() * n);
+    ENSURE(c, w.gpl, (size_t)plane_stride<D>() * n);
     ENSURE(c, c->req, n);
     {
         ProfScope ps(c, DMT_PROF_SETUP, st, n);
@@ -1009,7 +1010,7 @@ dmt_status dense_loop(dmt_context* c, Job& J, Ctl& out, hipStream_t st) {
         if (viol == 0 && tier >= 3) {
             kind = 2;
             if (m.n_desc_cells) {
-                k_scheck_desc<<<nblocks(m.n_desc_cells), TPB, 0, st>>>(fpl, gpl, P<int>(m.dcell), P<int>(m.dcbr),
+                k_scheck_desc<D><<<nblocks(m.n_desc_cells), TPB, 0, st>>>(fpl, gpl, P<int>(m.dcell), P<int>(m.dcbr),
                                                                        m.n_desc_cells, P<int>(m.dfirst));
                 k_starget<D><<<nblocks(m.n_desc), TPB, 0, st>>>(fpl, gpl, dm, 0, P<int>(m.dcell), P<int64_t>(m.doff),
                                                                 P<int>(m.dterm), (int)m.n_desc, P<int>(m.dfirst), tier,
@@ -1145,7 +1146,7 @@ int64_t workspace_estimate(int D, int64_t n, const dmt_options* o = nullptr) {
     // fields, state, f and g planes, frontier lists and stamps, separatrix branches (an upper
     // estimate of what the correction of one field allocates; the branches are data-dependent),
     // and the saddle-saddle walk's two level queues and edge stamps (7 edges per vertex, 4 B each)
-    int64_t est = (D == 2 ? 140 : 252) * n + (1 << 20);
+    int64_t est = (D == 2 ? 144 : 264) * n + (1 << 20);
     if (o && D == 3 && o->tier == 4 && (o->flags & DMT_F_SADDLE_SADDLE)) est += 84 * n;
     return est;
 }
@@ -1506,7 +1507,7 @@ dmt_status dmt_gradient_pairs(dmt_context* c, const dmt_grid* gr, const float* f
     int D;
     TRY(check_grid(c, gr, dm, D));
     HIPCHK(c, hipSetDevice(c->device));
-    ENSURE(c, c->gpl, (size_t)nplanes(D) * dm.n);
+    ENSURE(c, c->gpl, (size_t)plane_bytes(D) * dm.n);
     TRY(launch_grad(c, D, field, P<uint8_t>(c->gpl), dm, st));
     const int64_t o1 = dm.n, o2 = o1 + (int64_t)dm.n * ntypes(D, 1), o3 = o2 + (int64_t)dm.n * ntypes(D, 2);
     if (D == 2) k_export<2><<<nblocks(dm.n), TPB, 0, st>>>(P<uint8_t>(c->gpl), dm, o1, o2, o3, up, down);
@@ -1523,7 +1524,7 @@ dmt_status dmt_extract_msc(dmt_context* c, const dmt_grid* gr, const float* fiel
     int D;
     TRY(check_grid(c, gr, dm, D));
     HIPCHK(c, hipSetDevice(c->device));
-    ENSURE(c, c->gpl, (size_t)nplanes(D) * dm.n);
+    ENSURE(c, c->gpl, (size_t)plane_bytes(D) * dm.n);
     TRY(launch_grad(c, D, field, P<uint8_t>(c->gpl), dm, st));
     MscBufs& m = c->msc;
     TRY(D == 2 ? build_msc<2>(c, m, P<uint8_t>(c->gpl), dm, true, st)
@@ -1551,7 +1552,7 @@ dmt_status dmt_compare_msc(dmt_context* c, const dmt_grid* gr, const float* f, c
     int D;
     TRY(check_grid(c, gr, dm, D));
     HIPCHK(c, hipSetDevice(c->device));
-    const size_t planes = (size_t)nplanes(D) * dm.n;
+    const size_t planes = (size_t)plane_bytes(D) * dm.n;
     ENSURE(c, c->gpl, planes);
     ENSURE(c, c->gpl2, planes);
     TRY(launch_grad(c, D, f, P<uint8_t>(c->gpl), dm, st));

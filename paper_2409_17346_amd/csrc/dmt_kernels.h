@@ -25,6 +25,19 @@ constexpr uint8_t CODE_DOWN = 0x80;
 constexpr uint8_t CODE_NONE = 0xFF;
 constexpr int INF32 = 0x7fffffff;
 
+// Code planes are stored anchor-major: the codes of the cells anchored at vertex a (one per
+// plane, i.e. per cell type) are bytes [a * PS, a * PS + NB) of the array, PS = 8 in 2D (NB = 6)
+// and 32 in 3D (NB = 26); the other bytes are unused.  All codes of one anchor share one cache
+// line (and one page), which the scattered accesses of the correction loop rely on, and a dense
+// pass reads or writes one contiguous run per anchor.
+template <int D>
+constexpr int plane_stride() { return D == 2 ? 8 : 32; }
+
+template <int D>
+__host__ __device__ __forceinline__ size_t pidx(int p, int a) {
+    return (size_t)a * plane_stride<D>() + p;
+}
+
 struct Dims {
     int nx, ny, nz, nxy, n;
     // division by nx and by nxy as a multiply-high, add and shift (set_divisors):
@@ -292,13 +305,13 @@ __device__ __forceinline__ bool grad_vertex(const int v, const float* __restrict
     uint8_t old_v = 0;
     uint8_t old_t[NTRI];
     if constexpr (TRACK && D == 2) {
-        old_v = planes[v];
+        old_v = planes[pidx<D>(0, v)];
         static_for<0, NTRI>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
             constexpr int s = G<D>::g.tri_s[i], t = G<D>::g.tri_t[i];
             constexpr int as = G<D>::g.tri_anchor_slot[i];
             const bool ex = ((inside >> s) & 1) && ((inside >> t) & 1);
-            old_t[i] = planes[ex ? (size_t)G<D>::g.tri_plane[i] * dm.n + anchor_at<D, as>(v, dm) : (size_t)v];
+            old_t[i] = planes[ex ? pidx<D>(G<D>::g.tri_plane[i], anchor_at<D, as>(v, dm)) : pidx<D>(0, v)];
         });
     }
     // below[s] = lower neighbours that precede neighbour s (slot order = id order)
@@ -323,8 +336,8 @@ __device__ __forceinline__ bool grad_vertex(const int v, const float* __restrict
         if (((L >> s) & 1) && below[s] == 0) { m = s; vcode = CODE_UP | C27Rel<D, s, -1>::value; }
     });
     bool changed = false;
-    if constexpr (TRACK) changed = (D == 2 ? old_v : planes[v]) != vcode;
-    planes[v] = vcode;
+    if constexpr (TRACK) changed = (D == 2 ? old_v : planes[pidx<D>(0, v)]) != vcode;
+    planes[pidx<D>(0, v)] = vcode;
 
     // edges (v, s)
     int emin[NS];
@@ -347,7 +360,7 @@ __device__ __forceinline__ bool grad_vertex(const int v, const float* __restrict
                 }
             });
         }
-        planes[(size_t)G<D>::g.edge_plane[s] * dm.n + anchor_at<D, as>(v, dm)] = code;
+        planes[pidx<D>(G<D>::g.edge_plane[s], anchor_at<D, as>(v, dm))] = code;
     });
 
     // triangles (v, s, t)
@@ -376,7 +389,7 @@ __device__ __forceinline__ bool grad_vertex(const int v, const float* __restrict
                 });
             }
         }
-        uint8_t* const dst = &planes[(size_t)G<D>::g.tri_plane[i] * dm.n + anchor_at<D, as>(v, dm)];
+        uint8_t* const dst = &planes[pidx<D>(G<D>::g.tri_plane[i], anchor_at<D, as>(v, dm))];
         if constexpr (TRACK && D == 2) changed |= old_t[i] != code;
         *dst = code;
     });
@@ -396,7 +409,7 @@ __device__ __forceinline__ bool grad_vertex(const int v, const float* __restrict
             else if (t_s && !u_t) { low = t; tm = tmin[G<D>::g.tri_index[s][u]]; downc = CODE_DOWN | C27Rel<D, t, as>::value; }
             else { low = s; tm = tmin[G<D>::g.tri_index[t][u]]; downc = CODE_DOWN | C27Rel<D, s, as>::value; }
             const uint8_t code = (tm == low) ? downc : CODE_CRIT;
-            uint8_t* const dst = &planes[(size_t)G<D>::g.tet_plane[i] * dm.n + anchor_at<D, as>(v, dm)];
+            uint8_t* const dst = &planes[pidx<D>(G<D>::g.tet_plane[i], anchor_at<D, as>(v, dm))];
             if constexpr (TRACK) changed |= *dst != code;
             *dst = code;
         });
@@ -426,8 +439,8 @@ __device__ __forceinline__ void classify_plane(const Dims& dm, int a, int x, int
     constexpr int dim = g.bdim[P];
     if (tier == 1 && dim != 0 && dim != D) return;
     if (!cell_exists<D, P>(dm, x, y, z)) return;
-    const uint8_t fc = fpl[(size_t)P * dm.n + a];
-    const uint8_t gc = gpl[(size_t)P * dm.n + a];
+    const uint8_t fc = fpl[pidx<D>(P, a)];
+    const uint8_t gc = gpl[pidx<D>(P, a)];
     const bool fcrit = fc == CODE_CRIT, gcrit = gc == CODE_CRIT;
     if (fcrit == gcrit) return;
     int target;
@@ -462,7 +475,7 @@ __device__ __forceinline__ void classify_plane(const Dims& dm, int a, int x, int
                     fp = g.facet_plane[P][k];
                 }
             }
-            const uint8_t sc = fpl[(size_t)fp * dm.n + fa];
+            const uint8_t sc = fpl[pidx<D>(fp, fa)];
             best = fa + c27_lin(dm, sc & 63);
         }
         target = best;
@@ -683,7 +696,7 @@ template <int D, int P>
 __device__ __forceinline__ void crit_count_plane(const Dims& dm, const uint8_t* __restrict__ pl, int a, int x,
                                                  int y, int z, int* c) {
     constexpr auto& g = G<D>::g;
-    if (cell_exists<D, P>(dm, x, y, z) && pl[(size_t)P * dm.n + a] == CODE_CRIT) c[g.bdim[P]]++;
+    if (cell_exists<D, P>(dm, x, y, z) && pl[pidx<D>(P, a)] == CODE_CRIT) c[g.bdim[P]]++;
     if constexpr (P + 1 < Geom<D>::NB) crit_count_plane<D, P + 1>(dm, pl, a, x, y, z, c);
 }
 
@@ -691,7 +704,7 @@ template <int D, int P>
 __device__ __forceinline__ void crit_write_plane(const Dims& dm, const uint8_t* __restrict__ pl, int a, int x,
                                                  int y, int z, int* pos, int* const* out) {
     constexpr auto& g = G<D>::g;
-    if (cell_exists<D, P>(dm, x, y, z) && pl[(size_t)P * dm.n + a] == CODE_CRIT) {
+    if (cell_exists<D, P>(dm, x, y, z) && pl[pidx<D>(P, a)] == CODE_CRIT) {
         constexpr int d = g.bdim[P];
         out[d][pos[d]++] = a * g.ntypes[d] + (P - g.base[d]);
     }
@@ -752,7 +765,7 @@ __device__ __forceinline__ int top_id(int a, int tp) {
 // On a boundary exit sets a = -1.
 template <int D>
 __device__ __forceinline__ bool asc_step(const Dims& dm, const uint8_t* __restrict__ pl, int& a, int& tp) {
-    const uint8_t code = pl[(size_t)tp * dm.n + a];
+    const uint8_t code = pl[pidx<D>(tp, a)];
     if (code == CODE_CRIT) return false;
     const int c = code & 63;
     int x, y, z;
@@ -786,7 +799,7 @@ __global__ void __launch_bounds__(256) k_label_init(const uint8_t* __restrict__ 
     constexpr auto& g = G<D>::g;
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= dm.n) return;
-    const uint8_t vc = pl[a];
+    const uint8_t vc = pl[pidx<D>(0, a)];
     vlab[a] = vc == CODE_CRIT ? a : a + c27_lin(dm, vc & 63);
     int x, y, z;
     coords(dm, a, x, y, z);
@@ -875,7 +888,7 @@ __global__ void __launch_bounds__(256) k_desc_walk(const uint8_t* __restrict__ p
     for (;;) {
         if (mode) { cells[k] = v; cell_branch[k] = b; k++; }
         n++;
-        const uint8_t c = pl[v];
+        const uint8_t c = pl[pidx<D>(0, v)];
         if (c == CODE_CRIT) break;
         if (n >= dm.n) { atomicOr(err, 4u); break; }
         v += c27_lin(dm, c & 63);
@@ -950,13 +963,14 @@ __global__ void __launch_bounds__(256) k_asc_walk(const uint8_t* __restrict__ pl
 // its f pairing is the troublemaker; the apex of its f-pair is requested.  Tier 3 keeps only
 // branches whose g-path ends elsewhere than the f-path.
 
+template <int D>
 __global__ void __launch_bounds__(256) k_scheck_desc(const uint8_t* __restrict__ fpl, const uint8_t* __restrict__ gpl,
                                                      const int* __restrict__ cells, const int* __restrict__ cbr,
                                                      int64_t ncell, int* __restrict__ first) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= ncell) return;
     const int v = cells[k];
-    if (fpl[v] != gpl[v]) atomicMin(&first[cbr[k]], (int)k);
+    if (fpl[pidx<D>(0, v)] != gpl[pidx<D>(0, v)]) atomicMin(&first[cbr[k]], (int)k);
 }
 
 template <int D>
@@ -969,7 +983,7 @@ __global__ void __launch_bounds__(256) k_scheck_asc(const uint8_t* __restrict__ 
     const int T = cells[k];
     const int a = T / g.ntypes[D];
     const int tp = T - a * g.ntypes[D] + g.base[D];
-    const size_t o = (size_t)tp * dm.n + a;
+    const size_t o = pidx<D>(tp, a);
     if (fpl[o] != gpl[o]) atomicMin(&first[cbr[k]], (int)k);
 }
 
@@ -992,7 +1006,7 @@ __global__ void __launch_bounds__(256) k_starget(const uint8_t* __restrict__ fpl
             if (!asc) {
                 int v = cells[off[b]];
                 for (int step = 0; step < dm.n; step++) {
-                    const uint8_t cc = gpl[v];
+                    const uint8_t cc = gpl[pidx<D>(0, v)];
                     if (cc == CODE_CRIT) break;
                     v += c27_lin(dm, cc & 63);
                 }
@@ -1014,12 +1028,12 @@ __global__ void __launch_bounds__(256) k_starget(const uint8_t* __restrict__ fpl
             int target;
             if (!asc) {
                 const int v = cells[k];
-                target = v + c27_lin(dm, fpl[v] & 63);
+                target = v + c27_lin(dm, fpl[pidx<D>(0, v)] & 63);
             } else {
                 const int T = cells[k];
                 const int a = T / g.ntypes[D];
                 const int tp = T - a * g.ntypes[D] + g.base[D];
-                target = a + c27_lin(dm, fpl[(size_t)tp * dm.n + a] & 63);
+                target = a + c27_lin(dm, fpl[pidx<D>(tp, a)] & 63);
             }
             req[target] = 1;
             c = 1;
@@ -1040,7 +1054,7 @@ __device__ __forceinline__ void export_plane(const Dims& dm, const uint8_t* __re
     const int64_t id = (int64_t)a * g.ntypes[d] + (P - g.base[d]);
     int64_t u = -1, w = -1;
     if (cell_exists<D, P>(dm, x, y, z)) {
-        const uint8_t c = pl[(size_t)P * dm.n + a];
+        const uint8_t c = pl[pidx<D>(P, a)];
         const int cc = c & 63;
         if (c != CODE_CRIT && (c & CODE_UP)) {
 #pragma unroll

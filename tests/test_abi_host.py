@@ -44,8 +44,8 @@ def test_binding_refuses_cpu_tensors():
 
 def test_workspace_estimate():
     from paper_2409_17346_amd import dmt
-    assert dmt.dmt_workspace_bytes((128, 128)) == 140 * 128 * 128 + (1 << 20)
-    assert dmt.dmt_workspace_bytes((8, 9, 10)) == 252 * 720 + (1 << 20)
+    assert dmt.dmt_workspace_bytes((128, 128)) == 144 * 128 * 128 + (1 << 20)
+    assert dmt.dmt_workspace_bytes((8, 9, 10)) == 264 * 720 + (1 << 20)
     assert dmt.dmt_workspace_bytes((1, 9)) == -1
 
 

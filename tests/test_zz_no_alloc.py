@@ -91,7 +91,7 @@ def test_noalloc_limits(dmt):
         r = _noalloc(dmt, ctx, w, cap=n_ll)
         _same(r, ref)
         # fields whose workspace exceeds the scratch are refused before any work
-        side = 1000                              # 1.0 M vertices: 140 B each exceeds 128 MiB
+        side = 1000                              # 1.0 M vertices: 144 B each exceeds 128 MiB
         big = torch.zeros((side, side), device="cuda")
         assert dmt.dmt_workspace_bytes((side, side)) > dmt.DMT_NOALLOC_SCRATCH_BYTES
         with pytest.raises(dmt.DmtError) as e:
