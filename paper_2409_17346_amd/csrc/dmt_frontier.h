@@ -115,7 +115,10 @@ struct Ctl {
     P(unsigned) bstamp;       /* touched-branch stamps */                                          \
     P(int) tcl;               /* touched cells of the current iteration */                         \
     P(int) dbl;               /* touched branches of the current iteration */                      \
-    P(int) newmin;            /* per branch id: first touched cell that differs (INF32 between) */ \
+    /* per branch id: the first touched cell that differs, packed with its target (cell << 32 |   \
+       target; all ones between), and the target of the branch's first differing cell */          \
+    P(unsigned long long) newmin;                                                                  \
+    P(int) btgt;                                                                                   \
     /* branches whose first differing cell may be set (a superset of them), for the separatrix    \
        step; inlist marks the members */                                                           \
     P(int) cand[2];                                                                                \
@@ -423,27 +426,30 @@ constexpr uint32_t VM_DEAD = 1u << 31;
 // Every plane's codes are loaded unconditionally (plane P of anchor a is in bounds for every
 // anchor), so all loads are in flight together; planes whose cell does not exist, or that the
 // tier ignores, are masked afterwards.
-// With fpk (2D), the anchor's f codes are also returned packed (plane P in byte P) with bit 63
-// set, so its targets need not load them again.
+// The anchor's codes are read as whole 8-byte words (its group is 8-byte aligned).  With fpk
+// (2D), its f codes are also returned packed (plane P in byte P) with bit 63 set, so its targets
+// need not load them again.
 template <int D>
 __device__ __forceinline__ uint32_t vmask_anchor(const Dims& dm, int a, int x, int y, int z,
                                                  const uint8_t* __restrict__ fpl, const uint8_t* __restrict__ gpl,
                                                  int tier, uint64_t* fpk = nullptr) {
+    constexpr int W = plane_stride<D>() / 8;
+    uint64_t fw[W], gw[W];
+    const uint64_t* fp = reinterpret_cast<const uint64_t*>(fpl + pidx<D>(0, a));
+    const uint64_t* gp = reinterpret_cast<const uint64_t*>(gpl + pidx<D>(0, a));
+#pragma unroll
+    for (int k = 0; k < W; k++) {
+        fw[k] = fp[k];
+        gw[k] = gp[k];
+    }
     uint8_t fc[Geom<D>::NB], gc[Geom<D>::NB];
     static_for<0, Geom<D>::NB>([&](auto pc) {
         constexpr int P = decltype(pc)::value;
-        fc[P] = fpl[pidx<D>(P, a)];
-        gc[P] = gpl[pidx<D>(P, a)];
+        fc[P] = (uint8_t)(fw[P / 8] >> (8 * (P % 8)));
+        gc[P] = (uint8_t)(gw[P / 8] >> (8 * (P % 8)));
     });
     if constexpr (D == 2) {
-        if (fpk) {
-            uint64_t k = 1ull << 63;
-            static_for<0, Geom<D>::NB>([&](auto pc) {
-                constexpr int P = decltype(pc)::value;
-                k |= (uint64_t)fc[P] << (8 * P);
-            });
-            *fpk = k;
-        }
+        if (fpk) *fpk = fw[0] | (1ull << 63);   // byte 7 is padding
     }
     uint32_t m = 0;
     static_for<0, Geom<D>::NB>([&](auto pc) {
@@ -692,19 +698,32 @@ __device__ __forceinline__ void phase_grad(const FrontierView& B, const Dims& dm
     revive_pass<D, WG>(B, dm, it, gtid, gsize);
 }
 
-// First cell of f-branch k's cell range whose g pairing differs from f's, or INF32.
+// Whether branch cell k (descending: a vertex, ascending: a top cell) is paired differently in
+// g than in f; with tgt, also the troublemaker target it would have as its branch's first
+// differing cell: the apex of its f-pair, read from the same f code.
 template <int D>
-__device__ __forceinline__ bool branch_cell_differs(const FrontierView& B, const Dims& dm, bool asc, long long k) {
+__device__ __forceinline__ bool branch_cell_differs(const FrontierView& B, const Dims& dm, bool asc, long long k,
+                                                    int* tgt = nullptr) {
     constexpr auto& g = G<D>::g;
     if (!asc) {
         const int v = B.dcell[k];
-        return B.fpl[pidx<D>(0, v)] != B.gpl[pidx<D>(0, v)];
+        const uint8_t fc = B.fpl[pidx<D>(0, v)];
+        if (tgt) *tgt = v + c27_lin(dm, fc & 63);
+        return fc != B.gpl[pidx<D>(0, v)];
     }
     const int T = B.acell[k];
     const int a = T / g.ntypes[D];
     const int tp = T - a * g.ntypes[D] + g.base[D];
     const size_t o = pidx<D>(tp, a);
-    return B.fpl[o] != B.gpl[o];
+    const uint8_t fc = B.fpl[o];
+    if (tgt) *tgt = a + c27_lin(dm, fc & 63);
+    return fc != B.gpl[o];
+}
+
+constexpr unsigned long long NEWMIN_NONE = ~0ull;
+
+__device__ __forceinline__ unsigned long long newmin_pack(long long k, int target) {
+    return (unsigned long long)k << 32 | (unsigned)target;
 }
 
 // Keeping first[] (each f-branch's first cell whose g pairing differs) current, in two passes
@@ -728,7 +747,8 @@ __device__ __forceinline__ void touched_cells(const FrontierView& B, const Dims&
             const int k = asc ? kk - (int)B.n_dcell : kk;
             bb = asc ? B.n_desc + B.acbr[k] : B.dcbr[k];
             mine = atomicMax(&B.bstamp[bb], stamp) < stamp;
-            if (branch_cell_differs<D>(B, dm, asc, k)) atomicMin(&B.newmin[bb], k);
+            int t;
+            if (branch_cell_differs<D>(B, dm, asc, k, &t)) atomicMin(&B.newmin[bb], newmin_pack(k, t));
         }
         const int idx = wave_append(mine, &S.n_db);
         if (mine) B.dbl[idx] = bb;
@@ -737,7 +757,8 @@ __device__ __forceinline__ void touched_cells(const FrontierView& B, const Dims&
 
 // Pass B (phase_bscan): for each marked branch, if its old first cell still differs the new
 // first is the smaller of it and newmin; otherwise the first differing cell after the old first
-// (searched only up to newmin), else newmin.  One wave per branch, 64 cells per step.
+// (searched only up to newmin), else newmin.  One wave per branch, 64 cells per step.  The
+// target of the new first cell (btgt) comes from the code that decided it.
 template <int D, bool WG = false>
 __device__ __forceinline__ void phase_bscan(const FrontierView& B, const Dims& dm, int it, int gtid, int gsize) {
     if (it == 0 || B.tier < 3) return;
@@ -753,29 +774,38 @@ __device__ __forceinline__ void phase_bscan(const FrontierView& B, const Dims& d
         int* first = asc ? B.afirst : B.dfirst;
         const int64_t* off = asc ? B.aoff : B.doff;
         const int old = first[b];
-        const int nm = B.newmin[bb];
-        int res;
-        if (old != INF32 && branch_cell_differs<D>(B, dm, asc, old)) {
+        const unsigned long long nmp = B.newmin[bb];
+        const int nm = nmp == NEWMIN_NONE ? INF32 : (int)(nmp >> 32);
+        const int nmt = (int)(unsigned)nmp;
+        int res, rt;
+        int ot = 0;
+        if (old != INF32 && branch_cell_differs<D>(B, dm, asc, old, &ot)) {
             res = old < nm ? old : nm;
+            rt = old < nm ? ot : nmt;
         } else {
             res = nm;
+            rt = nmt;
             const long long hi = off[b + 1];
             const long long end = nm < hi ? nm : hi;
             long long k0 = old == INF32 ? end : (long long)old + 1;
             for (; k0 < end; k0 += 64) {
                 const long long k = k0 + lane;
-                const bool d = k < end && branch_cell_differs<D>(B, dm, asc, k);
+                int t = 0;
+                const bool d = k < end && branch_cell_differs<D>(B, dm, asc, k, &t);
                 const unsigned long long m = __ballot(d);
                 scanned += 64;
                 if (m) {
-                    res = (int)(k0 + __ffsll((long long)m) - 1);
+                    const int l = __ffsll((long long)m) - 1;
+                    res = (int)(k0 + l);
+                    rt = __shfl(t, l, 64);
                     break;
                 }
             }
         }
         if (lane == 0) {
             first[b] = res;
-            B.newmin[bb] = INF32;
+            B.btgt[bb] = rt;
+            B.newmin[bb] = NEWMIN_NONE;
             if (res != INF32 && !B.inlist[bb]) {
                 B.inlist[bb] = 1;
                 B.cand[sel][atomicAdd(n_cand_of<WG>(B, sel), 1)] = bb;
@@ -908,6 +938,7 @@ __device__ __forceinline__ void phase_sapply(const FrontierView& B, const Dims& 
             const int* cells = asc ? B.acell : B.dcell;
             const int* term = asc ? B.aterm : B.dterm;
             const int k = first[b];
+            const int tgt = B.btgt[bb];   // loaded beside first[b]; valid when it is set
             kept = k != INF32;
             if (!kept) B.inlist[bb] = 0;
             if (k != INF32) {
@@ -938,15 +969,7 @@ __device__ __forceinline__ void phase_sapply(const FrontierView& B, const Dims& 
                     ok = gt != term[b];
                 }
                 if (ok) {
-                    if (!asc) {
-                        const int v = cells[k];
-                        target = v + c27_lin(dm, B.fpl[pidx<D>(0, v)] & 63);
-                    } else {
-                        const int T = cells[k];
-                        const int a = T / g.ntypes[D];
-                        const int tp = T - a * g.ntypes[D] + g.base[D];
-                        target = a + c27_lin(dm, B.fpl[pidx<D>(tp, a)] & 63);
-                    }
+                    target = tgt;
                     c[asc ? 1 : 0]++;
                 }
             }
@@ -1123,6 +1146,7 @@ __device__ __forceinline__ void record_iteration(const FrontierView& B, int it, 
 
 // The first candidate list (list 0): the branches whose first differing cell the dense scan of
 // iteration 0 set.  ctl->n_cand[0] must be 0 before the launch.
+template <int D>
 __global__ void __launch_bounds__(256) k_fr_cand_init(FrontierBufs hb, Ctl* c) {
     const FrontierView& B = view(hb);
     const int nb = B.n_desc + B.n_asc;
@@ -1131,8 +1155,15 @@ __global__ void __launch_bounds__(256) k_fr_cand_init(FrontierBufs hb, Ctl* c) {
     if (i0 >= nb) return;
     bool set = false;
     if (i < nb) {
-        set = (i < B.n_desc ? B.dfirst[i] : B.afirst[i - B.n_desc]) != INF32;
+        const bool asc = i >= B.n_desc;
+        const int k = asc ? B.afirst[i - B.n_desc] : B.dfirst[i];
+        set = k != INF32;
         B.inlist[i] = set;
+        if (set) {
+            int t;
+            (void)branch_cell_differs<D>(B, B.dm, asc, k, &t);
+            B.btgt[i] = t;
+        }
     }
     const int idx = wave_append(set, &c->n_cand[0]);
     if (set) B.cand[0][idx] = i;

@@ -91,7 +91,7 @@ struct MscBufs {
 // Device state of one correction job.
 struct JobWs {
     DevBuf lo, g0, g1, state, fpl, gpl, vmask, vl0, vl1, dvl0, dvl1, dal0, dal1, vstamp, astamp, astamp1, rstamp;
-    DevBuf vpos, vstart, tsum, toff, ecell, bstamp, tcl, dbl, newmin, cand0, cand1, inlist;
+    DevBuf vpos, vstart, tsum, toff, ecell, bstamp, tcl, dbl, newmin, btgt, cand0, cand1, inlist;
     DevBuf ss_src, ss_q0, ss_q1, ss_stamp;
     DevBuf fofs, ftgt, dreq, frz;
     MscBufs msc;
@@ -99,7 +99,7 @@ struct JobWs {
         std::vector<DevBuf*> v = {&lo,     &g0,     &g1,      &state,  &fpl,   &gpl,   &vmask,  &vl0,
                                   &vl1,    &dvl0,   &dvl1,    &dal0,   &dal1,  &vstamp, &astamp, &astamp1,
                                   &rstamp, &vpos,   &vstart,  &tsum,   &toff,   &ecell, &bstamp, &tcl,
-                                  &dbl,    &newmin, &cand0,   &cand1,  &inlist, &ss_src, &ss_q0,  &ss_q1,
+                                  &dbl,    &newmin, &btgt,    &cand0,   &cand1,  &inlist, &ss_src, &ss_q0,  &ss_q1,
                                   &ss_stamp, &fofs, &ftgt,  &dreq,    &frz};
         for (DevBuf* b : msc.all()) v.push_back(b);
         return v;
@@ -591,11 +591,12 @@ dmt_status job_frontier(dmt_context* c, Job& J, Ctl* ctl, hipStream_t st) {
         ENSURE(c, w.tcl, sizeof(int) * (size_t)ne);
         ENSURE(c, w.bstamp, sizeof(unsigned) * (size_t)nbr);
         ENSURE(c, w.dbl, sizeof(int) * (size_t)nbr);
-        ENSURE(c, w.newmin, sizeof(int) * (size_t)nbr);
+        ENSURE(c, w.newmin, sizeof(unsigned long long) * (size_t)nbr);
+        ENSURE(c, w.btgt, sizeof(int) * (size_t)nbr);
         ENSURE(c, w.cand0, sizeof(int) * (size_t)nbr);
         ENSURE(c, w.cand1, sizeof(int) * (size_t)nbr);
         ENSURE(c, w.inlist, (size_t)nbr);
-        TRY(fill_i32(c, P<int>(w.newmin), nbr, INF32, st));
+        TRY(fill_i32(c, P<int>(w.newmin), 2 * nbr, -1, st));   // NEWMIN_NONE: all ones
         HIPCHK(c, hipMemsetAsync(w.vpos.p, 0, sizeof(int) * n, st));
         HIPCHK(c, hipMemsetAsync(w.bstamp.p, 0, sizeof(unsigned) * (size_t)nbr, st));
         // counting sort of the entries by vertex: counts, offsets, fill
@@ -617,7 +618,8 @@ dmt_status job_frontier(dmt_context* c, Job& J, Ctl* ctl, hipStream_t st) {
         B.bstamp = P<unsigned>(w.bstamp);
         B.tcl = P<int>(w.tcl);
         B.dbl = P<int>(w.dbl);
-        B.newmin = P<int>(w.newmin);
+        B.newmin = P<unsigned long long>(w.newmin);
+        B.btgt = P<int>(w.btgt);
         B.cand[0] = P<int>(w.cand0);
         B.cand[1] = P<int>(w.cand1);
         B.inlist = P<uint8_t>(w.inlist);
@@ -658,7 +660,7 @@ dmt_status job_iteration0(dmt_context* c, Job& J, hipStream_t st) {
     ProfScope ps(c, DMT_PROF_APPLY, st, 0);
     k_fr_vr<D><<<gfull, TPB, 0, st>>>(J.B, J.dm);
     const int64_t nbr = (int64_t)J.B.n_desc + J.B.n_asc;
-    if (nbr) k_fr_cand_init<<<nblocks(nbr), TPB, 0, st>>>(J.B, J.B.ctl);
+    if (nbr) k_fr_cand_init<D><<<nblocks(nbr), TPB, 0, st>>>(J.B, J.B.ctl);
     CHECK_LAUNCH(c);
     return DMT_OK;
 }
@@ -902,7 +904,7 @@ dmt_status run_phases(dmt_context* c, Job& J, hipStream_t st) {
         k_fr_classify0<D><<<nblocks(n), TPB, 0, st>>>(J.B, J.dm);
         k_fr_vr<D><<<gfull, TPB, 0, st>>>(J.B, J.dm);
         const int64_t nbr = (int64_t)J.B.n_desc + J.B.n_asc;
-        if (nbr) k_fr_cand_init<<<nblocks(nbr), TPB, 0, st>>>(J.B, J.B.ctl);
+        if (nbr) k_fr_cand_init<D><<<nblocks(nbr), TPB, 0, st>>>(J.B, J.B.ctl);
         if (J.o.tier >= 3) k_fr_sapply<D><<<gfull, TPB, 0, st>>>(J.B, J.dm);
         if (J.B.ss_on) k_fr_ss<<<1, 1024, 0, st>>>(J.B, J.dm);
         k_fr_finish<<<1, 1, 0, st>>>(J.B);
