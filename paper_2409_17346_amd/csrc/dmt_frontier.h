@@ -1463,23 +1463,33 @@ __global__ void __launch_bounds__(256) k_fr_grad(FrontierBufs hb, Dims dm) {
 // the list of violating anchors in vl[0], compacted by wave ballot and a block-wide prefix sum with
 // one atomic per block; the violation pass of iteration 0 then requests targets for the listed
 // anchors only.
+constexpr int CLASSIFY_APB = 1024;   // anchors per block of k_fr_classify0
 template <int D>
 __global__ void __launch_bounds__(256) k_fr_classify0(FrontierBufs hb, Dims dm) {
     const FrontierView& B = view(hb);
-    const int a = blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t m = 0;
-    if (a < dm.n) {
-        int x, y, z;
-        coords(dm, a, x, y, z);
-        m = vmask_anchor<D>(dm, a, x, y, z, B.fpl, B.gpl, B.tier);
-        B.vmask[a] = m;
+    // a block takes CLASSIFY_APB consecutive anchors, thread t those at t + k * 256 (coalesced)
+    uint32_t m[CLASSIFY_APB / 256];
+    int c = 0;
+#pragma unroll
+    for (int k = 0; k < CLASSIFY_APB / 256; k++) {
+        const int a = blockIdx.x * CLASSIFY_APB + k * 256 + threadIdx.x;
+        m[k] = 0;
+        if (a < dm.n) {
+            int x, y, z;
+            coords(dm, a, x, y, z);
+            m[k] = vmask_anchor<D>(dm, a, x, y, z, B.fpl, B.gpl, B.tier);
+            B.vmask[a] = m[k];
+        }
+        c += m[k] != 0;
     }
     __shared__ int base_sh;
     int total;
-    const int off = block_exclusive_scan(m != 0 ? 1 : 0, total);
+    int off = block_exclusive_scan(c, total);
     if (threadIdx.x == 0 && total) base_sh = atomicAdd(&B.ctl->n_v0, total);
     __syncthreads();
-    if (m != 0) B.vl[0][base_sh + off] = a;
+#pragma unroll
+    for (int k = 0; k < CLASSIFY_APB / 256; k++)
+        if (m[k] != 0) B.vl[0][base_sh + off++] = blockIdx.x * CLASSIFY_APB + k * 256 + threadIdx.x;
 }
 
 template <int D>

@@ -653,7 +653,7 @@ dmt_status job_iteration0(dmt_context* c, Job& J, hipStream_t st) {
     }
     {
         ProfScope ps(c, DMT_PROF_CLASSIFY, st, n);
-        k_fr_classify0<D><<<nblocks(n), TPB, 0, st>>>(J.B, J.dm);
+        k_fr_classify0<D><<<(unsigned)((n + CLASSIFY_APB - 1) / CLASSIFY_APB), TPB, 0, st>>>(J.B, J.dm);
         CHECK_LAUNCH(c);
     }
     // the requests (and edits) of iteration 0's violations
@@ -901,7 +901,7 @@ dmt_status run_phases(dmt_context* c, Job& J, hipStream_t st) {
     {
         ProfScope ps(c, DMT_PROF_LOOP, st, 0);
         k_fr_grad<D><<<gfull, TPB, 0, st>>>(J.B, J.dm);
-        k_fr_classify0<D><<<nblocks(n), TPB, 0, st>>>(J.B, J.dm);
+        k_fr_classify0<D><<<(unsigned)((n + CLASSIFY_APB - 1) / CLASSIFY_APB), TPB, 0, st>>>(J.B, J.dm);
         k_fr_vr<D><<<gfull, TPB, 0, st>>>(J.B, J.dm);
         const int64_t nbr = (int64_t)J.B.n_desc + J.B.n_asc;
         if (nbr) k_fr_cand_init<D><<<nblocks(nbr), TPB, 0, st>>>(J.B, J.B.ctl);
