@@ -23,6 +23,10 @@
 
 namespace dmt {
 
+// The dirty-vertex, affected-anchor (two parities) and request stamps of a vertex are one
+// 16-byte record: vstamp, astamp[0], astamp[1] and rstamp point at its words 0..3.
+constexpr int STAMP_STRIDE = 4;
+
 // Per-iteration counters live in slot it % 3: iteration it fills its own slot and the list
 // lengths of slot (it+1) % 3; slot (it+1) % 3 is cleared when iteration it begins (its last
 // readers belong to iteration it-2).  List buffers alternate by iteration parity.
@@ -78,6 +82,8 @@ struct Ctl {
     P(int) vl[2];             /* violation anchor lists */                                         \
     P(int) dvl[2];            /* dirty vertex lists */                                             \
     P(int) dal[2];            /* affected anchor lists */                                          \
+    /* per-vertex stamps, interleaved in one array (entry i of each at [STAMP_STRIDE * i]) so   \
+       that the claims around one vertex touch one cache line and one page: */                    \
     P(unsigned) vstamp;       /* dirty-vertex stamps */                                            \
     /* affected-anchor stamps by iteration parity: iteration k's in [k & 1]; the edits of         \
        iteration k mark [(k+1) & 1] while [k & 1] is still read */                                 \
@@ -326,7 +332,7 @@ __device__ __forceinline__ void mark_neighbourhood(const FrontierView& B, const 
                         (unsigned)(sz + dz) < (unsigned)dm.nz;
         const int t = vv + dx + dm.nx * dy + dm.nxy * dz;
         bool won = false;
-        if (ok) won = atomicMax((ring ? B.vstamp : B.astamp[nxt]) + t, stamp) < stamp;
+        if (ok) won = atomicMax((ring ? B.vstamp : B.astamp[nxt]) + (size_t)STAMP_STRIDE * t, stamp) < stamp;
         const int iv = wave_append(won && ring, &N1.n_dv);
         const int ia = wave_append(won && !ring, &N1.n_da);
         if (won) {
@@ -352,7 +358,7 @@ __device__ __forceinline__ void mark_neighbourhood(const FrontierView& B, const 
             const bool ok = (unsigned)(x + dx) < (unsigned)dm.nx && (unsigned)(y + dy) < (unsigned)dm.ny &&
                             (unsigned)(z + dz) < (unsigned)dm.nz;
             okv |= (uint32_t)ok << s;
-            ov[s] = atomicMax(vs + (ok ? v + dx + dm.nx * dy + dm.nxy * dz : v), ok ? stamp : 0u);
+            ov[s] = atomicMax(vs + (size_t)STAMP_STRIDE * (ok ? v + dx + dm.nx * dy + dm.nxy * dz : v), ok ? stamp : 0u);
         }
 #pragma unroll
         for (int j = 0; j < NA; j++) {
@@ -360,7 +366,7 @@ __device__ __forceinline__ void mark_neighbourhood(const FrontierView& B, const 
             const bool ok = x + dx >= 0 && y + dy >= 0 && z + dz >= 0 && x + dx < dm.nx && y + dy < dm.ny &&
                             z + dz < dm.nz;
             oka |= (uint64_t)ok << j;
-            oa[j] = atomicMax(as + (ok ? v + dx + dm.nx * dy + dm.nxy * dz : v), ok ? stamp : 0u);
+            oa[j] = atomicMax(as + (size_t)STAMP_STRIDE * (ok ? v + dx + dm.nx * dy + dm.nxy * dz : v), ok ? stamp : 0u);
         }
 #pragma unroll
         for (int s = 0; s < NV; s++)
@@ -406,7 +412,7 @@ __device__ __forceinline__ void request_apply(const FrontierView& B, const Dims&
         const float ghv = B.gh[v], l = B.lo[v];
         const unsigned dq = frozen ? B.dreq[v] : 0u;
         if (floored) *floored &= (st & 0x80) != 0;
-        if (atomicMax(&B.rstamp[v], stamp) < stamp) {
+        if (atomicMax(&B.rstamp[(size_t)STAMP_STRIDE * v], stamp) < stamp) {
             if (dq == 0) rc[0]++;
             if (edit) changed = apply_vertex(B, v, it, st, ghv, l);
             if (changed) rc[1]++;
@@ -871,7 +877,7 @@ __device__ __forceinline__ void phase_vr(const FrontierView& B, const Dims& dm, 
             B.vmask[a] = m;
         } else if (i0 < ntot) {
             a = vlist[i0 - na];
-            if (astamp[a] != astamp_it) {
+            if (astamp[(size_t)STAMP_STRIDE * a] != astamp_it) {
                 const uint32_t mv = B.vmask[a];
                 m = mv & VM_PLANES;
                 old_quiet = mv & VM_QUIET;

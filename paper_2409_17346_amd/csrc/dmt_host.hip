@@ -90,15 +90,15 @@ struct MscBufs {
 
 // Device state of one correction job.
 struct JobWs {
-    DevBuf lo, g0, g1, state, fpl, gpl, vmask, vl0, vl1, dvl0, dvl1, dal0, dal1, vstamp, astamp, astamp1, rstamp;
+    DevBuf lo, g0, g1, state, fpl, gpl, vmask, vl0, vl1, dvl0, dvl1, dal0, dal1, stamps;
     DevBuf vpos, vstart, tsum, toff, ecell, bstamp, tcl, dbl, newmin, btgt, cand0, cand1, inlist;
     DevBuf ss_src, ss_q0, ss_q1, ss_stamp;
     DevBuf fofs, ftgt, dreq, frz;
     MscBufs msc;
     std::vector<DevBuf*> all() {
         std::vector<DevBuf*> v = {&lo,     &g0,     &g1,      &state,  &fpl,   &gpl,   &vmask,  &vl0,
-                                  &vl1,    &dvl0,   &dvl1,    &dal0,   &dal1,  &vstamp, &astamp, &astamp1,
-                                  &rstamp, &vpos,   &vstart,  &tsum,   &toff,   &ecell, &bstamp, &tcl,
+                                  &vl1,    &dvl0,   &dvl1,    &dal0,   &dal1,  &stamps, &vpos,   &vstart,
+                                  &tsum,   &toff,   &ecell,   &bstamp, &tcl,
                                   &dbl,    &newmin, &btgt,    &cand0,   &cand1,  &inlist, &ss_src, &ss_q0,  &ss_q1,
                                   &ss_stamp, &fofs, &ftgt,  &dreq,    &frz};
         for (DevBuf* b : msc.all()) v.push_back(b);
@@ -518,10 +518,7 @@ dmt_status job_frontier(dmt_context* c, Job& J, Ctl* ctl, hipStream_t st) {
     ENSURE(c, w.dvl1, sizeof(int) * n);
     ENSURE(c, w.dal0, sizeof(int) * n);
     ENSURE(c, w.dal1, sizeof(int) * n);
-    ENSURE(c, w.vstamp, sizeof(unsigned) * n);
-    ENSURE(c, w.astamp, sizeof(unsigned) * n);
-    ENSURE(c, w.astamp1, sizeof(unsigned) * n);
-    ENSURE(c, w.rstamp, sizeof(unsigned) * n);
+    ENSURE(c, w.stamps, sizeof(unsigned) * STAMP_STRIDE * n);
     // frozen anchors: targets of up to 4 violations per vertex on average, then none freeze more
     const int64_t ftgt_cap = std::max<int64_t>(4 * (int64_t)n, 1 << 16);
     ENSURE(c, w.fofs, sizeof(int) * n);
@@ -530,10 +527,7 @@ dmt_status job_frontier(dmt_context* c, Job& J, Ctl* ctl, hipStream_t st) {
     ENSURE(c, w.frz, sizeof(int) * n);
     HIPCHK(c, hipMemsetAsync(w.dreq.p, 0, sizeof(unsigned) * n, st));
     HIPCHK(c, hipMemcpyAsync(w.g1.p, w.g0.p, sizeof(float) * n, hipMemcpyDeviceToDevice, st));
-    HIPCHK(c, hipMemsetAsync(w.vstamp.p, 0, sizeof(unsigned) * n, st));
-    HIPCHK(c, hipMemsetAsync(w.astamp.p, 0, sizeof(unsigned) * n, st));
-    HIPCHK(c, hipMemsetAsync(w.astamp1.p, 0, sizeof(unsigned) * n, st));
-    HIPCHK(c, hipMemsetAsync(w.rstamp.p, 0, sizeof(unsigned) * n, st));
+    HIPCHK(c, hipMemsetAsync(w.stamps.p, 0, sizeof(unsigned) * STAMP_STRIDE * n, st));
     k_fr_init<<<1, 1, 0, st>>>(ctl);
     CHECK_LAUNCH(c);
 
@@ -557,10 +551,10 @@ dmt_status job_frontier(dmt_context* c, Job& J, Ctl* ctl, hipStream_t st) {
     B.dvl[1] = P<int>(w.dvl1);
     B.dal[0] = P<int>(w.dal0);
     B.dal[1] = P<int>(w.dal1);
-    B.vstamp = P<unsigned>(w.vstamp);
-    B.astamp[0] = P<unsigned>(w.astamp);
-    B.astamp[1] = P<unsigned>(w.astamp1);
-    B.rstamp = P<unsigned>(w.rstamp);
+    B.vstamp = P<unsigned>(w.stamps);
+    B.astamp[0] = P<unsigned>(w.stamps) + 1;
+    B.astamp[1] = P<unsigned>(w.stamps) + 2;
+    B.rstamp = P<unsigned>(w.stamps) + 3;
     B.fofs = P<int>(w.fofs);
     B.ftgt = P<int>(w.ftgt);
     B.dreq = P<unsigned>(w.dreq);
