@@ -19,6 +19,8 @@
 // and their targets are edited after one grid-wide synchronisation.  Lists are filled with
 // wave-aggregated appends.  The output is bit-identical to the dense form and to the oracle.
 #pragma once
+#include <cstddef>
+
 #include "dmt_kernels.h"
 
 namespace dmt {
@@ -32,12 +34,16 @@ constexpr int STAMP_STRIDE = 4;
 // readers belong to iteration it-2).  List buffers alternate by iteration parity.
 struct Slot {
     unsigned long long cnt[CNT_WORDS];  // log record layout
+    // n_dv and n_da are adjacent and 8-byte aligned: both are reserved with one 64-bit atomic
     int n_dv, n_da, n_vl;   // dirty vertices, affected anchors, violation list of this iteration
     int n_tc;               // branch cells of f on a dirty vertex whose codes changed (touched)
     int n_db;               // branches with a touched cell
     int n_scan;             // branch cells examined to settle those branches
     int n_frz;              // listed anchors frozen by this iteration (freeze list length)
 };
+
+static_assert(offsetof(Slot, n_dv) % 8 == 0 && offsetof(Slot, n_da) == offsetof(Slot, n_dv) + 4,
+              "n_dv, n_da reserved as one 64-bit word");
 
 struct Ctl {
     int it;                 // current iteration
@@ -193,6 +199,32 @@ __device__ __forceinline__ int wave_append_n(int k, int* counter) {
     return base + incl - k;
 }
 
+// Two appends at once to a pair of adjacent counters (pair[0], pair[1], 8-byte aligned): k0 and
+// k1 slots per lane (each below 2^10), one scan and one 64-bit atomic per wave; whole waves call
+// it.  Returns the lane's first index in each list through i0 and i1.
+__device__ __forceinline__ void wave_append_pair(int k0, int k1, int* pair, int& i0, int& i1) {
+    const int lane = __lane_id();
+    const int k = k0 | k1 << 16;
+    int incl = k;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += t;
+    }
+    const int total = __shfl(incl, 63, 64);
+    unsigned long long base = 0;
+    if (total != 0) {
+        if (lane == 63)
+            base = atomicAdd(reinterpret_cast<unsigned long long*>(pair),
+                             (unsigned long long)(unsigned)(total & 0xffff) |
+                                 (unsigned long long)(unsigned)(total >> 16) << 32);
+        base = __shfl(base, 63, 64);
+    }
+    const int ex = incl - k;
+    i0 = (int)(unsigned)base + (ex & 0xffff);
+    i1 = (int)(base >> 32) + (ex >> 16);
+}
+
 // Lists are walked in rounds of gsize items, item base + gtid in a round; a wave whose first
 // item lies past the end leaves the loop (a wave-uniform test, so wave-level collectives in the
 // body stay safe), which keeps idle waves from competing with working ones for issue slots.
@@ -333,8 +365,16 @@ __device__ __forceinline__ void mark_neighbourhood(const FrontierView& B, const 
         const int t = vv + dx + dm.nx * dy + dm.nxy * dz;
         bool won = false;
         if (ok) won = atomicMax((ring ? B.vstamp : B.astamp[nxt]) + (size_t)STAMP_STRIDE * t, stamp) < stamp;
-        const int iv = wave_append(won && ring, &N1.n_dv);
-        const int ia = wave_append(won && !ring, &N1.n_da);
+        // both appends with one 64-bit atomic on the adjacent counters n_dv, n_da
+        const unsigned long long bv = __ballot(won && ring), ba = __ballot(won && !ring);
+        unsigned long long base = 0;
+        if (__lane_id() == 0 && (bv | ba))
+            base = atomicAdd(reinterpret_cast<unsigned long long*>(&N1.n_dv),
+                             (unsigned long long)__popcll(bv) | (unsigned long long)__popcll(ba) << 32);
+        base = __shfl(base, 0, 64);
+        const unsigned long long below = (1ull << __lane_id()) - 1ull;
+        const int iv = (int)(unsigned)base + __popcll(bv & below);
+        const int ia = (int)(base >> 32) + __popcll(ba & below);
         if (won) {
             if (ring) B.dvl[nxt][iv] = t;
             else B.dal[nxt][ia] = t;
@@ -375,8 +415,8 @@ __device__ __forceinline__ void mark_neighbourhood(const FrontierView& B, const 
         for (int j = 0; j < NA; j++)
             if (((oka >> j) & 1ull) && oa[j] < stamp) ma |= 1ull << j;
     }
-    int iv = wave_append_n(__popc(mv), &N1.n_dv);
-    int ia = wave_append_n(__popcll(ma), &N1.n_da);
+    int iv, ia;
+    wave_append_pair(__popc(mv), __popcll(ma), &N1.n_dv, iv, ia);
     if (!changed) return;
     int* dv = B.dvl[nxt];
     int* da = B.dal[nxt];
