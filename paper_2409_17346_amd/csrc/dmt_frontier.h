@@ -469,10 +469,9 @@ constexpr uint32_t VM_PLANES = (1u << 26) - 1u;
 constexpr uint32_t VM_QUIET = 1u << 30;
 constexpr uint32_t VM_DEAD = 1u << 31;
 
-// Every plane's codes are loaded unconditionally (plane P of anchor a is in bounds for every
-// anchor), so all loads are in flight together; planes whose cell does not exist, or that the
-// tier ignores, are masked afterwards.
-// The anchor's codes are read as whole 8-byte words (its group is 8-byte aligned).  With fpk
+// Violation mask of anchor a.  The anchor's codes are read as whole 8-byte words (its group is
+// 8-byte aligned and in bounds for every anchor), all loads in flight together; planes whose
+// cell does not exist, or that the tier ignores, are masked afterwards.  With fpk
 // (2D), its f codes are also returned packed (plane P in byte P) with bit 63 set, so its targets
 // need not load them again.
 template <int D>

@@ -4,8 +4,9 @@
 //   f, g_hat, g, lo        fp32[N]
 //   state                  u8[N]   bits 0-2 quantized edit count q, bit 7 set once floored
 //   req                    u8[N]   1 = vertex requested for an edit this iteration
-//   gradient planes        u8[NB][N] (code byte of the cell of plane p anchored at each vertex;
-//                          see dmt_geom.h), one set for f (built once) and one for g
+//   gradient codes         u8[N][PS], anchor-major (byte p of vertex a's group is the code of
+//                          the cell of plane p anchored at a, see dmt_geom.h; PS = 8 in 2D, 32
+//                          in 3D), one array for f (built once) and one for g
 // Every kernel is data parallel with no cross-thread ordering: requests are idempotent
 // byte stores and are only consumed by a later kernel (Jacobi semantics), counters are
 // reduced in LDS and added to global 64-bit counters.
