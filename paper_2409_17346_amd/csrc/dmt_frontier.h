@@ -25,6 +25,12 @@
 
 namespace dmt {
 
+// A full-grid iteration is dense when its lists cover more than 1/DENSE_DIV of the grid; a dense
+// violation pass after an iteration that edited more than 1/NOMARK_DIV of the vertices marks no
+// neighbourhoods.
+constexpr int DENSE_DIV = 16;
+constexpr int NOMARK_DIV = 32;
+
 // The dirty-vertex, affected-anchor (two parities) and request stamps of a vertex are one
 // 16-byte record: vstamp, astamp[0], astamp[1] and rstamp point at its words 0..3.
 constexpr int STAMP_STRIDE = 4;
@@ -60,7 +66,10 @@ struct Ctl {
     unsigned long long dead_distinct;
     int n_ftgt;
     int n_dead;             // frozen anchors (in LDS while the resident loop runs)
-    int n_v0;               // violating anchors of iteration 0 (k_fr_classify0), listed in vl[0]
+    int n_v0;               // violating anchors of a dense iteration (k_fr_classify0), listed in vl[it & 1]
+    // full-grid form: the current iteration is dense (every vertex and anchor, see phase_grad);
+    // nomark: the last violation pass made no dirty/affected lists, so the next iteration is dense
+    int dense, nomark;
     Slot slot[3];
 };
 
@@ -440,9 +449,11 @@ __device__ __forceinline__ void mark_neighbourhood(const FrontierView& B, const 
 // With floored, *floored is cleared unless v is already at its floor (final).  With frozen (the
 // job has frozen anchors), a vertex that frozen violations request (dreq[v] > 0) is counted among
 // their distinct targets instead.
+// Without mark (a violation pass whose next iteration is dense), the neighbourhood is not marked.
 template <int D, bool WG = false>
 __device__ __forceinline__ void request_apply(const FrontierView& B, const Dims& dm, int v, int it, bool edit,
-                                              int* rc, bool* floored = nullptr, bool frozen = false) {
+                                              int* rc, bool* floored = nullptr, bool frozen = false,
+                                              bool mark = true) {
     const unsigned stamp = (unsigned)it + 1u;
     bool changed = false;
     if (v >= 0) {
@@ -458,7 +469,7 @@ __device__ __forceinline__ void request_apply(const FrontierView& B, const Dims&
             if (changed) rc[1]++;
         }
     }
-    mark_neighbourhood<D, WG>(B, dm, changed, v, it);
+    if (mark) mark_neighbourhood<D, WG>(B, dm, changed, v, it);   // mark is uniform over the wave
 }
 
 // ---- violation mask of one anchor: planes whose criticality differs between f and g --------
@@ -587,7 +598,7 @@ __device__ __forceinline__ int plane_target_any(int p, const FrontierView& B, co
 template <int D, bool WG = false>
 __device__ __forceinline__ void anchor_requests(const FrontierView& B, const Dims& dm, int a, uint32_t m, int it,
                                                 bool edit, int* cnt, int* rc, bool& quiet, bool frozen,
-                                                bool track_quiet, uint64_t fpk = 0) {
+                                                bool track_quiet, uint64_t fpk = 0, bool mark = true) {
     const float* gcur = B.gb[it & 1];
     for (;;) {
         if (__ballot(m != 0) == 0) break;
@@ -597,7 +608,7 @@ __device__ __forceinline__ void anchor_requests(const FrontierView& B, const Dim
             m &= m - 1u;
             target = plane_target_any<D>(p, B, dm, a, gcur, cnt, fpk);
         }
-        request_apply<D, WG>(B, dm, target, it, edit, rc, track_quiet ? &quiet : nullptr, frozen);
+        request_apply<D, WG>(B, dm, target, it, edit, rc, track_quiet ? &quiet : nullptr, frozen, mark);
     }
 }
 
@@ -712,6 +723,39 @@ __device__ __forceinline__ void phase_grad(const FrontierView& B, const Dims& dm
         return;
     }
     Slot& S = slot_of<WG>(B, it);
+    if constexpr (!WG) {
+        // Dense iteration (full-grid form): when the last violation pass made no lists, or its
+        // lists cover more than 1/DENSE_DIV of the grid, every vertex's gradient is recomputed and
+        // copied across, and the violation pass classifies every anchor, as at iteration 0.  The
+        // frozen anchors are all revived (their masks are recomputed) and the first differing
+        // cell of every branch is found afresh.  It is the frontier iteration with every vertex
+        // dirty and every anchor affected, which gives the same result.
+        Ctl* c = B.ctl;
+        const bool dense = ld_relaxed(&c->nomark) != 0 ||
+                           (long long)ld_relaxed(&S.n_dv) + ld_relaxed(&S.n_da) > (long long)dm.n / DENSE_DIV;
+        if (gtid == 0) c->dense = dense;
+        if (dense) {
+            if (gtid == 0) {
+                c->n_v0 = 0;
+                c->cand_sel = 0;
+                c->n_cand[0] = c->n_cand[1] = 0;
+                c->n_dead = 0;
+                for (int k = 0; k < 8; k++) c->dead_cnt[k] = 0;
+                c->dead_distinct = 0;
+                c->n_ftgt = 0;
+            }
+            for (int i = gtid; i < dm.n; i += gsize) {
+                grad_vertex<D>(i, gcur, B.gpl, dm);
+                gnext[i] = gcur[i];
+                if (B.dreq) B.dreq[i] = 0u;
+            }
+            if (B.tier >= 3) {
+                for (int k = gtid; k < B.n_desc; k += gsize) B.dfirst[k] = INF32;
+                for (int k = gtid; k < B.n_asc; k += gsize) B.afirst[k] = INF32;
+            }
+            return;
+        }
+    }
     const int n = ld_relaxed(&S.n_dv);
     const int* list = B.dvl[it & 1];
     // With branch tracking, the branch cells on each dirty vertex whose vertex or top-cell codes
@@ -879,9 +923,20 @@ __device__ __forceinline__ void phase_vr(const FrontierView& B, const Dims& dm, 
     // One index space: the affected anchors (every anchor at iteration 0) get new masks; the
     // anchors listed by the previous iteration and not affected since keep theirs.
     // iteration 0: only the violating anchors the classification pass listed (masks computed)
-    const int na = it == 0 ? ld_relaxed(&B.ctl->n_v0) : ld_relaxed(&S.n_da);
-    const int nl = it == 0 ? 0 : ld_relaxed(&S.n_vl);
+    // a dense iteration (iteration 0, or one the full-grid form's gradient pass made dense) takes
+    // the violating anchors the classification pass listed, with their masks
+    bool dense = it == 0;
+    if constexpr (!WG) dense = dense || ld_relaxed(&B.ctl->dense) != 0;
+    const int na = dense ? ld_relaxed(&B.ctl->n_v0) : ld_relaxed(&S.n_da);
+    const int nl = dense ? 0 : ld_relaxed(&S.n_vl);
     const int ntot = na + nl;
+    // a dense iteration after the first, whose previous iteration edited more than 1/NOMARK_DIV
+    // of the vertices, marks no neighbourhoods (its own edits will be about as many): its next
+    // iteration is dense too, and the full-grid form runs it.  Violations at floored targets edit
+    // nothing, so a field stalled at its floors goes back to frontier iterations, which freeze them.
+    const bool mark = !(dense && it > 0 &&
+                        (long long)ld_relaxed(&slot_of<WG>(B, it - 1).cnt[CNT_CHANGED]) > (long long)dm.n / NOMARK_DIV);
+    if (!WG && gtid == 0) B.ctl->nomark = !mark;
     const int* alist = B.dal[it & 1];
     const int* vlist = B.vl[it & 1];
     const unsigned astamp_it = (unsigned)it;
@@ -905,8 +960,8 @@ __device__ __forceinline__ void phase_vr(const FrontierView& B, const Dims& dm, 
         uint64_t fpk = 0;   // the anchor's f codes, when loaded here (2D)
         int a = 0;
         bool listed = false;
-        if (i0 < na && it == 0) {
-            a = B.vl[0][i0];
+        if (i0 < na && dense) {
+            a = B.vl[it & 1][i0];
             m = B.vmask[a];
         } else if (i0 < na) {
             a = alist[i0];
@@ -931,7 +986,7 @@ __device__ __forceinline__ void phase_vr(const FrontierView& B, const Dims& dm, 
         const int fi = wave_append(frz, n_frz);
         if (frz) B.frz[fi] = a;
         bool quiet = true;
-        anchor_requests<D, WG>(B, dm, a, m, it, edit, cnt, rc, quiet, frozen, FREEZE, fpk);
+        anchor_requests<D, WG>(B, dm, a, m, it, edit, cnt, rc, quiet, frozen, FREEZE, fpk, mark);
         // the quiet bit is rewritten only when it changes (rarely)
         if constexpr (FREEZE) {
             const uint32_t qb = (m != 0 && quiet) ? VM_QUIET : 0u;
@@ -942,7 +997,7 @@ __device__ __forceinline__ void phase_vr(const FrontierView& B, const Dims& dm, 
     // branch at iteration 0 (first[] starts at INF32), afterwards the branches listed by the
     // gradient pass
     if (B.tier >= 3) {
-        if (it == 0) {
+        if (dense) {
             for (long long k = gtid; k < B.n_dcell; k += gsize)
                 if (branch_cell_differs<D>(B, dm, false, k)) atomicMin(&B.dfirst[B.dcbr[k]], (int)k);
             for (long long k = gtid; k < B.n_acell; k += gsize)
@@ -969,6 +1024,7 @@ __device__ __forceinline__ void phase_sapply(const FrontierView& B, const Dims& 
     const int nb = ld_relaxed(n_cand_of<WG>(B, sel));
     const int* cl = B.cand[sel];
     int* keep = B.cand[sel ^ 1];
+    const bool mark = WG || ld_relaxed(&B.ctl->nomark) == 0;   // set by this iteration's violation pass
     for (int base = 0; base < nb; base += gsize) {
         if (wave_done(base, gtid, nb)) break;
         const int i0 = base + gtid;
@@ -1021,7 +1077,7 @@ __device__ __forceinline__ void phase_sapply(const FrontierView& B, const Dims& 
         }
         const int idx = wave_append(kept, n_cand_of<WG>(B, sel ^ 1));
         if (kept) keep[idx] = bb;
-        request_apply<D, WG>(B, dm, target, it, edit, rc);
+        request_apply<D, WG>(B, dm, target, it, edit, rc, nullptr, false, mark);
     }
     add_counters<WG, 2>(slot_of<WG>(B, it).cnt + CNT_TM_DESC, c);
     add_counters<WG, 2>(slot_of<WG>(B, it).cnt + CNT_NREQ, rc);
@@ -1119,8 +1175,9 @@ __device__ __forceinline__ int ss_walk(const uint8_t* fpl, const uint8_t* gpl, c
 template <bool WG>
 __device__ __forceinline__ void phase_ss(const FrontierView& B, const Dims& dm, int it, bool edit, int tid, int nt) {
     int rc[2] = {0, 0};
+    const bool mark = WG || ld_relaxed(&B.ctl->nomark) == 0;
     int c = ss_walk(B.fpl, B.gpl, dm, B.ss_src, B.n_ss_src, B.ss_q[0], B.ss_q[1], B.ss_stamp, (unsigned)it + 1u,
-                    tid, nt, [&](int target) { request_apply<3, WG>(B, dm, target, it, edit, rc); });
+                    tid, nt, [&](int target) { request_apply<3, WG>(B, dm, target, it, edit, rc, nullptr, false, mark); });
     add_counters<WG, 1>(slot_of<WG>(B, it).cnt + CNT_TM_SS, &c);
     add_counters<WG, 2>(slot_of<WG>(B, it).cnt + CNT_NREQ, rc);
 }
@@ -1194,6 +1251,7 @@ __device__ __forceinline__ void record_iteration(const FrontierView& B, int it, 
 template <int D>
 __global__ void __launch_bounds__(256) k_fr_cand_init(FrontierBufs hb, Ctl* c) {
     const FrontierView& B = view(hb);
+    if (ld_relaxed(&c->done) || (ld_relaxed(&c->it) != 0 && ld_relaxed(&c->dense) == 0)) return;
     const int nb = B.n_desc + B.n_asc;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int i0 = i - (int)(threadIdx.x & 63u);
@@ -1228,6 +1286,7 @@ __global__ void k_fr_init(Ctl* c) {
     c->n_ftgt = 0;
     c->n_dead = 0;
     c->n_v0 = 0;
+    c->dense = c->nomark = 0;
     for (int i = 0; i < 3; i++) {
         for (int k = 0; k < CNT_WORDS; k++) c->slot[i].cnt[k] = 0;
         c->slot[i].n_dv = c->slot[i].n_da = c->slot[i].n_vl = c->slot[i].n_db = 0;
@@ -1314,6 +1373,9 @@ __device__ __forceinline__ void run_job_wg(const FrontierView& B, int max_passes
     const int tid = threadIdx.x, nt = blockDim.x;
     if (ld_relaxed(&c->done)) return;
     int it = ld_relaxed(&c->it);
+    // the full-grid violation pass before this launch made no lists: the next iteration is dense
+    // and is left to the grid
+    const bool nomark_in = ld_relaxed(&c->nomark) != 0;
     constexpr int SLOT_WORDS = (int)(3 * sizeof(Slot) / sizeof(int));
     static_assert(sizeof(Slot) % sizeof(int) == 0, "slots copied as ints");
     {
@@ -1358,7 +1420,7 @@ __device__ __forceinline__ void run_job_wg(const FrontierView& B, int max_passes
         // a large next iteration is left to full-grid launches: pause before its gradient pass
         if (st == 0 && big > 0) {
             const Slot& N = wg_slots[(it + 1) % 3];
-            if (N.n_da + N.n_vl > big) {
+            if (N.n_da + N.n_vl > big || nomark_in) {
                 if (tid == 0) c->paused = 1;
                 act = 4;
             }
@@ -1512,6 +1574,10 @@ constexpr int CLASSIFY_APB = 1024;   // anchors per block of k_fr_classify0
 template <int D>
 __global__ void __launch_bounds__(256) k_fr_classify0(FrontierBufs hb, Dims dm) {
     const FrontierView& B = view(hb);
+    if (!running(B.ctl)) return;
+    const int it = ld_relaxed(&B.ctl->it);
+    if (it != 0 && ld_relaxed(&B.ctl->dense) == 0) return;   // iteration 0 and dense iterations only
+    int* list = B.vl[it & 1];
     // a block takes CLASSIFY_APB consecutive anchors, thread t those at t + k * 256 (coalesced)
     uint32_t m[CLASSIFY_APB / 256];
     int c = 0;
@@ -1534,7 +1600,7 @@ __global__ void __launch_bounds__(256) k_fr_classify0(FrontierBufs hb, Dims dm) 
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < CLASSIFY_APB / 256; k++)
-        if (m[k] != 0) B.vl[0][base_sh + off++] = blockIdx.x * CLASSIFY_APB + k * 256 + threadIdx.x;
+        if (m[k] != 0) list[base_sh + off++] = blockIdx.x * CLASSIFY_APB + k * 256 + threadIdx.x;
 }
 
 template <int D>
