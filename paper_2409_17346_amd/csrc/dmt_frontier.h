@@ -66,7 +66,7 @@ struct Ctl {
     unsigned long long dead_distinct;
     int n_ftgt;
     int n_dead;             // frozen anchors (in LDS while the resident loop runs)
-    int n_v0;               // violating anchors of a dense iteration (k_fr_classify0), listed in vl[it & 1]
+    int n_v0;               // violating anchors of iteration 0 (k_fr_classify0), listed in vl[0]
     // full-grid form: the current iteration is dense (every vertex and anchor, see phase_grad);
     // nomark: the last violation pass made no dirty/affected lists, so the next iteration is dense
     int dense, nomark;
@@ -851,6 +851,12 @@ __device__ __forceinline__ void touched_cells(const FrontierView& B, const Dims&
 template <int D, bool WG = false>
 __device__ __forceinline__ void phase_bscan(const FrontierView& B, const Dims& dm, int it, int gtid, int gsize) {
     if (it == 0 || B.tier < 3) return;
+    if constexpr (!WG) {
+        if (ld_relaxed(&B.ctl->dense)) {   // first[] was found afresh by the dense scan
+            cand_rebuild<D>(B, gtid, gsize);
+            return;
+        }
+    }
     Slot& S = slot_of<WG>(B, it);
     const int n = ld_relaxed(&S.n_db);
     const int lane = __lane_id();
@@ -920,14 +926,15 @@ __device__ __forceinline__ void phase_vr(const FrontierView& B, const Dims& dm, 
     int* next = B.vl[(it + 1) & 1];
     int cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     int rc[2] = {0, 0};
-    // One index space: the affected anchors (every anchor at iteration 0) get new masks; the
-    // anchors listed by the previous iteration and not affected since keep theirs.
-    // iteration 0: only the violating anchors the classification pass listed (masks computed)
-    // a dense iteration (iteration 0, or one the full-grid form's gradient pass made dense) takes
-    // the violating anchors the classification pass listed, with their masks
-    bool dense = it == 0;
-    if constexpr (!WG) dense = dense || ld_relaxed(&B.ctl->dense) != 0;
-    const int na = dense ? ld_relaxed(&B.ctl->n_v0) : ld_relaxed(&S.n_da);
+    // One index space: the affected anchors get new masks; the anchors listed by the previous
+    // iteration and not affected since keep theirs.  Iteration 0 takes the violating anchors the
+    // classification pass listed (masks computed there); a dense iteration after it (full-grid
+    // form, see phase_grad) takes every anchor as affected.
+    const bool first = it == 0;
+    bool all = false;
+    if constexpr (!WG) all = !first && ld_relaxed(&B.ctl->dense) != 0;
+    const bool dense = first || all;
+    const int na = first ? ld_relaxed(&B.ctl->n_v0) : all ? dm.n : ld_relaxed(&S.n_da);
     const int nl = dense ? 0 : ld_relaxed(&S.n_vl);
     const int ntot = na + nl;
     // a dense iteration after the first, whose previous iteration edited more than 1/NOMARK_DIV
@@ -960,11 +967,11 @@ __device__ __forceinline__ void phase_vr(const FrontierView& B, const Dims& dm, 
         uint64_t fpk = 0;   // the anchor's f codes, when loaded here (2D)
         int a = 0;
         bool listed = false;
-        if (i0 < na && dense) {
-            a = B.vl[it & 1][i0];
+        if (i0 < na && first) {
+            a = B.vl[0][i0];
             m = B.vmask[a];
         } else if (i0 < na) {
-            a = alist[i0];
+            a = all ? i0 : alist[i0];
             int x, y, z;
             coords(dm, a, x, y, z);
             m = vmask_anchor<D>(dm, a, x, y, z, B.fpl, B.gpl, B.tier, &fpk);
@@ -1248,28 +1255,36 @@ __device__ __forceinline__ void record_iteration(const FrontierView& B, int it, 
 
 // The first candidate list (list 0): the branches whose first differing cell the dense scan of
 // iteration 0 set.  ctl->n_cand[0] must be 0 before the launch.
+// The troublemaker candidate list rebuilt from first[] (after a dense scan): the branches whose
+// first differing cell is set, with their targets, into list 0 (ctl->n_cand[0] = 0 and
+// ctl->cand_sel = 0 before).  Threads gtid, gtid + gsize, ... take branch ids; whole waves call it.
+template <int D>
+__device__ __forceinline__ void cand_rebuild(const FrontierView& B, int gtid, int gsize) {
+    const int nb = B.n_desc + B.n_asc;
+    for (int base = 0; base < nb; base += gsize) {
+        if (wave_done(base, gtid, nb)) break;
+        const int i = base + gtid;
+        bool set = false;
+        if (i < nb) {
+            const bool asc = i >= B.n_desc;
+            const int k = asc ? B.afirst[i - B.n_desc] : B.dfirst[i];
+            set = k != INF32;
+            B.inlist[i] = set;
+            if (set) {
+                int t;
+                (void)branch_cell_differs<D>(B, B.dm, asc, k, &t);
+                B.btgt[i] = t;
+            }
+        }
+        const int idx = wave_append(set, &B.ctl->n_cand[0]);
+        if (set) B.cand[0][idx] = i;
+    }
+}
+
+// The first candidate list, after the dense scan of iteration 0.
 template <int D>
 __global__ void __launch_bounds__(256) k_fr_cand_init(FrontierBufs hb, Ctl* c) {
-    const FrontierView& B = view(hb);
-    if (ld_relaxed(&c->done) || (ld_relaxed(&c->it) != 0 && ld_relaxed(&c->dense) == 0)) return;
-    const int nb = B.n_desc + B.n_asc;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int i0 = i - (int)(threadIdx.x & 63u);
-    if (i0 >= nb) return;
-    bool set = false;
-    if (i < nb) {
-        const bool asc = i >= B.n_desc;
-        const int k = asc ? B.afirst[i - B.n_desc] : B.dfirst[i];
-        set = k != INF32;
-        B.inlist[i] = set;
-        if (set) {
-            int t;
-            (void)branch_cell_differs<D>(B, B.dm, asc, k, &t);
-            B.btgt[i] = t;
-        }
-    }
-    const int idx = wave_append(set, &c->n_cand[0]);
-    if (set) B.cand[0][idx] = i;
+    cand_rebuild<D>(view(hb), blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
 }
 
 __global__ void k_fr_init(Ctl* c) {
@@ -1574,10 +1589,7 @@ constexpr int CLASSIFY_APB = 1024;   // anchors per block of k_fr_classify0
 template <int D>
 __global__ void __launch_bounds__(256) k_fr_classify0(FrontierBufs hb, Dims dm) {
     const FrontierView& B = view(hb);
-    if (!running(B.ctl)) return;
-    const int it = ld_relaxed(&B.ctl->it);
-    if (it != 0 && ld_relaxed(&B.ctl->dense) == 0) return;   // iteration 0 and dense iterations only
-    int* list = B.vl[it & 1];
+    int* list = B.vl[0];
     // a block takes CLASSIFY_APB consecutive anchors, thread t those at t + k * 256 (coalesced)
     uint32_t m[CLASSIFY_APB / 256];
     int c = 0;

@@ -695,14 +695,9 @@ dmt_status grid_iterations(dmt_context* c, const FrontierBufs& B, const Dims& dm
         if (B.ss_on) k_fr_ss<<<1, 1024, 0, st>>>(B, dm);
         k_fr_finish<<<1, 1, 0, st>>>(B);
     }
-    const unsigned gcls = (unsigned)((dm.n + CLASSIFY_APB - 1) / CLASSIFY_APB);
-    const int64_t nbr = (int64_t)B.n_desc + B.n_asc;
     for (int k = 0; k <= K; k++) {
-        // classification and candidate list return at once unless the iteration is dense
         k_fr_grad<D><<<gfull, TPB, 0, st>>>(B, dm);
-        k_fr_classify0<D><<<gcls, TPB, 0, st>>>(B, dm);
         k_fr_vr<D><<<gfull, TPB, 0, st>>>(B, dm);
-        if (nbr) k_fr_cand_init<D><<<nblocks(nbr), TPB, 0, st>>>(B, B.ctl);
         k_fr_bscan<D><<<gfull, TPB, 0, st>>>(B, dm);
         if (k == K) break;
         if (B.tier >= 3) k_fr_sapply<D><<<gfull, TPB, 0, st>>>(B, dm);
@@ -915,11 +910,8 @@ dmt_status run_phases(dmt_context* c, Job& J, hipStream_t st) {
         J.B.log = P<long long>(c->dlog);
         for (int b = 0; b < batch; b++) {
             ProfScope ps(c, DMT_PROF_LOOP, st, 0);
-            const int64_t nbr = (int64_t)J.B.n_desc + J.B.n_asc;
             k_fr_grad<D><<<gfull, TPB, 0, st>>>(J.B, J.dm);
-            k_fr_classify0<D><<<(unsigned)((n + CLASSIFY_APB - 1) / CLASSIFY_APB), TPB, 0, st>>>(J.B, J.dm);
             k_fr_vr<D><<<gfull, TPB, 0, st>>>(J.B, J.dm);
-            if (nbr) k_fr_cand_init<D><<<nblocks(nbr), TPB, 0, st>>>(J.B, J.B.ctl);
             k_fr_bscan<D><<<gfull, TPB, 0, st>>>(J.B, J.dm);
             if (J.o.tier >= 3) k_fr_sapply<D><<<gfull, TPB, 0, st>>>(J.B, J.dm);
             if (J.B.ss_on) k_fr_ss<<<1, 1024, 0, st>>>(J.B, J.dm);
