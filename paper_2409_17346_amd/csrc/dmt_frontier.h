@@ -28,7 +28,7 @@ namespace dmt {
 // A full-grid iteration is dense when its lists cover more than 1/DENSE_DIV of the grid; a dense
 // violation pass after an iteration that edited more than 1/NOMARK_DIV of the vertices marks no
 // neighbourhoods.
-constexpr int DENSE_DIV = 16;
+constexpr int DENSE_DIV = 4;
 constexpr int NOMARK_DIV = 32;
 
 // The dirty-vertex, affected-anchor (two parities) and request stamps of a vertex are one
@@ -1241,11 +1241,13 @@ __device__ __forceinline__ void record_iteration(const FrontierView& B, int it, 
         for (int k = 1; k < CNT_NREQ; k++) rec[k] = (long long)ld_relaxed(&S.cnt[k]);
         rec[CNT_NREQ] = (long long)ld_relaxed(&S.cnt[CNT_NREQ]);
         rec[CNT_CHANGED] = (long long)ld_relaxed(&S.cnt[CNT_CHANGED]);
-        rec[13] = it == 0 ? 0 : ld_relaxed(&S.n_dv);
-        rec[14] = it == 0 ? 0 : ld_relaxed(&S.n_da);
-        rec[15] = it == 0 ? 0 : ld_relaxed(&S.n_vl);
+        // a dense iteration's passes took every vertex as dirty and every anchor as affected
+        const bool dense = it > 0 && ld_relaxed(&c->dense) != 0;
+        rec[13] = it == 0 ? 0 : dense ? B.dm.n : ld_relaxed(&S.n_dv);
+        rec[14] = it == 0 ? 0 : dense ? B.dm.n : ld_relaxed(&S.n_da);
+        rec[15] = it == 0 || dense ? 0 : ld_relaxed(&S.n_vl);
         rec[16] = ld_relaxed(&S.n_db);
-        rec[17] = ld_relaxed(&S.n_scan);
+        rec[17] = ld_relaxed(&S.n_scan) + (dense && B.tier >= 3 ? B.n_dcell + B.n_acell : 0);   // dense: every branch cell
         rec[18] = it == 0 ? 0 : ld_relaxed(&S.n_tc);
         rec[19] = 0;
         rec[20] = (long long)ld_relaxed(&S.cnt[CNT_TM_SS]);
@@ -1332,8 +1334,9 @@ __device__ __forceinline__ unsigned long long c_total_wg(const Slot& S) {
 // ct: the iteration's critical-cell violations (c_total_wg of its slot).  Every lane reads the
 // counters it needs from LDS itself (the slot is final: the passes that fill it are behind a
 // barrier).
+// dense: the iteration's passes ran densely on the full grid (the loop's first decision only).
 __device__ __forceinline__ int wave_decide(const FrontierView& B, int it, int lane, unsigned long long ct,
-                                           long long* rec) {
+                                           long long* rec, bool dense = false) {
     const Slot& S = wg_slots[it % 3];
     const unsigned long long v = lane < CNT_WORDS ? S.cnt[lane] : 0ull;
     const unsigned long long tm_ss = S.cnt[CNT_TM_SS];
@@ -1347,11 +1350,11 @@ __device__ __forceinline__ int wave_decide(const FrontierView& B, int it, int la
     long long r = 0;
     if (lane == 0) r = ct ? 1 : 2;
     else if (lane <= CNT_CHANGED) r = (long long)v;
-    else if (lane == 13) r = S.n_dv;
-    else if (lane == 14) r = S.n_da;
-    else if (lane == 15) r = S.n_vl;
+    else if (lane == 13) r = dense ? B.dm.n : S.n_dv;
+    else if (lane == 14) r = dense ? B.dm.n : S.n_da;
+    else if (lane == 15) r = dense ? 0 : S.n_vl;
     else if (lane == 16) r = S.n_db;
-    else if (lane == 17) r = S.n_scan;
+    else if (lane == 17) r = S.n_scan + (dense && B.tier >= 3 ? B.n_dcell + B.n_acell : 0);
     else if (lane == 18) r = S.n_tc;
     else if (lane == 20) r = (long long)tm_ss;
     *rec = r;
@@ -1391,6 +1394,9 @@ __device__ __forceinline__ void run_job_wg(const FrontierView& B, int max_passes
     // the full-grid violation pass before this launch made no lists: the next iteration is dense
     // and is left to the grid
     const bool nomark_in = ld_relaxed(&c->nomark) != 0;
+    // the passes of iteration it (the one decided first) ran densely on the full grid
+    const bool dense_in = it > 0 && ld_relaxed(&c->dense) != 0;
+    const int it_in = it;
     constexpr int SLOT_WORDS = (int)(3 * sizeof(Slot) / sizeof(int));
     static_assert(sizeof(Slot) % sizeof(int) == 0, "slots copied as ints");
     {
@@ -1429,7 +1435,7 @@ __device__ __forceinline__ void run_job_wg(const FrontierView& B, int max_passes
     };
     // wave 0: decides iteration it (state_sh: 0 go on, 1-3 done, 4 pause before the next one)
     auto decide = [&](unsigned long long ct) {
-        const int st = wave_decide(B, it, tid, ct, &rec);
+        const int st = wave_decide(B, it, tid, ct, &rec, dense_in && it == it_in);
         if (tid == 19) rec = (long long)(wall_clock64() - t_it);
         int act = st;
         // a large next iteration is left to full-grid launches: pause before its gradient pass
