@@ -654,7 +654,7 @@ dmt_status job_iteration0(dmt_context* c, Job& J, hipStream_t st) {
     ProfScope ps(c, DMT_PROF_APPLY, st, 0);
     k_fr_vr<D><<<gfull, TPB, 0, st>>>(J.B, J.dm);
     const int64_t nbr = (int64_t)J.B.n_desc + J.B.n_asc;
-    if (nbr) k_fr_cand_init<D><<<nblocks(nbr), TPB, 0, st>>>(J.B, J.B.ctl);
+    if (nbr) k_fr_cand_init<D><<<nblocks((nbr + CAND_PER_THREAD - 1) / CAND_PER_THREAD), TPB, 0, st>>>(J.B, J.B.ctl);
     CHECK_LAUNCH(c);
     return DMT_OK;
 }
@@ -898,7 +898,7 @@ dmt_status run_phases(dmt_context* c, Job& J, hipStream_t st) {
         k_fr_classify0<D><<<(unsigned)((n + CLASSIFY_APB - 1) / CLASSIFY_APB), TPB, 0, st>>>(J.B, J.dm);
         k_fr_vr<D><<<gfull, TPB, 0, st>>>(J.B, J.dm);
         const int64_t nbr = (int64_t)J.B.n_desc + J.B.n_asc;
-        if (nbr) k_fr_cand_init<D><<<nblocks(nbr), TPB, 0, st>>>(J.B, J.B.ctl);
+        if (nbr) k_fr_cand_init<D><<<nblocks((nbr + CAND_PER_THREAD - 1) / CAND_PER_THREAD), TPB, 0, st>>>(J.B, J.B.ctl);
         if (J.o.tier >= 3) k_fr_sapply<D><<<gfull, TPB, 0, st>>>(J.B, J.dm);
         if (J.B.ss_on) k_fr_ss<<<1, 1024, 0, st>>>(J.B, J.dm);
         k_fr_finish<<<1, 1, 0, st>>>(J.B);
