@@ -185,6 +185,33 @@ def test_correct_hybrid_handoff(ctx, dmt, limit, case):
     assert (log[:, 14] + log[:, 15] > limit).any(), "the hand-off was not exercised"
 
 
+@pytest.mark.parametrize("case", ["extreme64", "tiny3d", "atoms3d40"])
+def test_correct_dense_iterations(ctx, dmt, case):
+    """With every iteration handed to the full grid, the iterations whose lists cover more than a
+    quarter of the grid run densely (every vertex dirty, every anchor affected), and a dense
+    iteration after one that edited more than 1/32 of the vertices makes no lists (its successor
+    is dense too): results and log stay those of the oracle, and the log shows both kinds."""
+    if case == "extreme64":
+        w = synth.extreme_noise2d(64, 1)
+    elif case == "tiny3d":
+        w = synth.tiny_cases(13, (12, 10, 9), rel=0.05, kind="smooth", ghat="noise")
+    else:
+        w = synth.config_atoms3d(seed=3, side=40, n_atoms=24)
+    dmt.dmt_set_tuning(ctx, {"loop_threads": [1024, 512], "handoff_anchors": [1, 1], "grid_iterations": [4, 64]})
+    try:
+        r, o = _compare_correction(ctx, dmt, w)
+    finally:
+        dmt.dmt_set_tuning(ctx, None)
+    n = w.f.size
+    log = r.log.numpy()
+    dense = log[:, 13] == n              # a dense iteration counts every vertex as dirty
+    dense[0] = False                     # iteration 0 is dense by construction
+    assert dense.any(), "no dense iteration"
+    assert (~dense[1:]).any(), "no frontier iteration"
+    unmarked = [it for it in range(2, len(log)) if dense[it] and log[it - 1, 12] > n // 32]
+    assert unmarked, "no dense iteration without lists"
+
+
 def _assert_stall_explained(w, g, tier, n_residual):
     """Every violation left at a stall has an equal-floor, both-at-floor pair of vertices ordered
     against f in the closed 1-ring of the cell's highest vertex: decrease-only edits can never
