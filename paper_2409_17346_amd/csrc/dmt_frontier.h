@@ -809,6 +809,38 @@ __device__ __forceinline__ bool branch_cell_differs(const FrontierView& B, const
     return fc != B.gpl[o];
 }
 
+// Dense scan for the first differing cell of every branch (first[] at INF32 before): lane k of
+// a wave takes cell base + k, so a wave covers consecutive cells, and the cells of one branch are
+// consecutive; only the first differing cell of each branch run within the wave lowers first[]
+// (one atomic per run instead of one per differing cell, which on a field where most cells
+// differ put many atomics on one address).
+template <int D>
+__device__ __forceinline__ void dense_first_scan(const FrontierView& B, const Dims& dm, bool asc, int gtid,
+                                                 int gsize) {
+    const long long n = asc ? B.n_acell : B.n_dcell;
+    const int* cbr = asc ? B.acbr : B.dcbr;
+    int* first = asc ? B.afirst : B.dfirst;
+    const int lane = __lane_id();
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (long long k0 = gtid - lane; k0 < n; k0 += gsize) {   // k0: the wave's first cell
+        const long long k = k0 + lane;
+        const bool in = k < n;
+        const int br = in ? cbr[k] : -1;
+        const bool d = in && branch_cell_differs<D>(B, dm, asc, k);
+        const int prev = __shfl_up(br, 1, 64);
+        const unsigned long long starts = __ballot(lane == 0 || br != prev);   // first lane of each run
+        const unsigned long long diff = __ballot(d);
+        if (d) {
+            // this lane's run starts at the highest start at or below it; an earlier differing
+            // lane of the same run holds the run's minimum
+            const int run0 = 63 - __clzll(starts & (below | (1ull << lane)));
+            const unsigned long long earlier = diff & below;
+            const int prevd = earlier ? 63 - __clzll(earlier) : -1;
+            if (prevd < run0) atomicMin(&first[br], (int)k);
+        }
+    }
+}
+
 constexpr unsigned long long NEWMIN_NONE = ~0ull;
 
 __device__ __forceinline__ unsigned long long newmin_pack(long long k, int target) {
@@ -1005,10 +1037,8 @@ __device__ __forceinline__ void phase_vr(const FrontierView& B, const Dims& dm, 
     // gradient pass
     if (B.tier >= 3) {
         if (dense) {
-            for (long long k = gtid; k < B.n_dcell; k += gsize)
-                if (branch_cell_differs<D>(B, dm, false, k)) atomicMin(&B.dfirst[B.dcbr[k]], (int)k);
-            for (long long k = gtid; k < B.n_acell; k += gsize)
-                if (branch_cell_differs<D>(B, dm, true, k)) atomicMin(&B.afirst[B.acbr[k]], (int)k);
+            dense_first_scan<D>(B, dm, false, gtid, gsize);
+            dense_first_scan<D>(B, dm, true, gtid, gsize);
         } else {
             touched_cells<D, WG>(B, dm, it, gtid, gsize);
         }
