@@ -233,19 +233,24 @@ dmt_status dmt_correct_noalloc(dmt_context *ctx, const dmt_grid *grid, const flo
 
 /* Launch shapes of the correction loop (Section 4.8: the GPU form of the C/S loops).  They change
  * speed only: every setting gives bit-identical results.  Index 0 is for 2D jobs, 1 for 3D jobs,
- * except grid_iterations: 0 for dmt_correct, 1 for batches and the server.
+ * except grid_iterations: 0 for calls that run one job (dmt_correct), 1 for calls that run
+ * several (batches, server rounds).
  *   loop_threads     threads of the workgroup that runs one job's loop: 512 or 1024 for 2D,
  *                    256 or 512 for 3D (fewer threads leave more registers per lane);
- *   handoff_anchors  an iteration with more affected plus listed anchors than this (or a
- *                    troublemaker pass over more candidate branches) leaves the workgroup and runs
- *                    as full-grid launches, one per phase; 0 never hands off;
- *   grid_iterations  iterations run as full-grid launches per hand-off (1..4096).
- * Defaults: {1024, 512}, {8192, 8192}, {4, 64}.  The autotuner of the Python package picks them
- * per workload by timing candidates. */
+ *   handoff_anchors  in calls that run one job, an iteration with more affected plus listed
+ *                    anchors than this (or a troublemaker pass over more candidate branches)
+ *                    leaves the workgroup and runs as full-grid launches, one per phase; 0 never
+ *                    hands off;
+ *   grid_iterations  iterations run as full-grid launches per hand-off (1..4096);
+ *   batch_handoff_anchors  the hand-off limit of calls that run several jobs (a paused job waits
+ *                    for the other workgroups, so batches favour fewer, larger hand-offs).
+ * Defaults: {1024, 512}, {8192, 1024}, {4, 64}, {8192, 8192}.  The autotuner of the Python
+ * package picks them per workload by timing candidates. */
 typedef struct {
     int32_t loop_threads[2];
     int32_t handoff_anchors[2];
     int32_t grid_iterations[2];
+    int32_t batch_handoff_anchors[2];
 } dmt_tuning;
 
 /* Sets the launch shapes of later calls on ctx (NULL restores the defaults).  DMT_E_INVALID for

@@ -16,14 +16,17 @@ import torch
 
 from . import dmt
 
-# (knob, index) -> candidate values; index 0/1 = 2D/3D jobs (grid_iterations: single/batch)
+# (knob, index) -> candidate values; index 0/1 = 2D/3D jobs (grid_iterations: single/batch);
+# single calls tune handoff_anchors, batches batch_handoff_anchors
 CANDIDATES: Dict[Tuple[str, int], Sequence[int]] = {
     ("loop_threads", 0): (1024, 512),
     ("loop_threads", 1): (512, 256),
     ("handoff_anchors", 0): (2048, 8192, 32768),
-    ("handoff_anchors", 1): (2048, 8192, 32768),
+    ("handoff_anchors", 1): (1024, 8192, 32768),
     ("grid_iterations", 0): (2, 4, 16),
     ("grid_iterations", 1): (16, 64, 256),
+    ("batch_handoff_anchors", 0): (2048, 8192, 32768),
+    ("batch_handoff_anchors", 1): (2048, 8192, 32768),
 }
 
 
@@ -32,7 +35,7 @@ def _knobs_for(dims: Sequence[int], batch: bool) -> List[Tuple[str, int]]:
     out = []
     for d in sorted(set(dims)):
         i = d - 2
-        out += [("loop_threads", i), ("handoff_anchors", i)]
+        out += [("loop_threads", i), ("batch_handoff_anchors" if batch else "handoff_anchors", i)]
     out.append(("grid_iterations", 1 if batch else 0))
     return out
 

@@ -115,9 +115,11 @@ dmt_tuning default_tuning() {
     t.loop_threads[0] = 1024;
     t.loop_threads[1] = 512;
     t.handoff_anchors[0] = 8192;
-    t.handoff_anchors[1] = 8192;
+    t.handoff_anchors[1] = 1024;
     t.grid_iterations[0] = 4;
     t.grid_iterations[1] = 64;
+    t.batch_handoff_anchors[0] = 8192;
+    t.batch_handoff_anchors[1] = 8192;
     return t;
 }
 }  // namespace
@@ -753,11 +755,13 @@ dmt_status run_wg(dmt_context* c, std::vector<Job*>& jobs, bool with_log, hipStr
     // launches (a workgroup takes about 1 us per 100 such anchors, the grid far less); the loop
     // kernel ends once every job has finished or paused, then the host runs a few iterations of
     // each paused job on the whole grid and launches the loop again
-    const int big2 = c->tune.handoff_anchors[0], big3 = c->tune.handoff_anchors[1];
+    // a paused job of a batch waits for every other workgroup to finish or pause before the
+    // host can run its grid iterations, so batches hand off less often and hand over more
+    // iterations at a time
+    const int32_t* big = nj == 1 ? c->tune.handoff_anchors : c->tune.batch_handoff_anchors;
+    const int big2 = big[0], big3 = big[1];
     std::vector<int> pos(nj);
     for (int k = 0; k < nj; k++) pos[order[k]] = k;
-    // a paused job of a batch waits for every other workgroup to finish or pause before the
-    // host can run its grid iterations, so batches hand over more iterations at a time
     const int grid_batch = c->tune.grid_iterations[nj == 1 ? 0 : 1];
     int64_t progress = -1;
     for (int launch = 0; max_launches < 0 || launch < max_launches; launch++) {
@@ -1722,7 +1726,8 @@ dmt_status dmt_set_tuning(dmt_context* c, const dmt_tuning* t) {
         (t->loop_threads[1] != 256 && t->loop_threads[1] != 512))
         return fail(c, DMT_E_INVALID, "loop_threads must be 512 or 1024 (2D) and 256 or 512 (3D)");
     for (int k = 0; k < 2; k++) {
-        if (t->handoff_anchors[k] < 0) return fail(c, DMT_E_INVALID, "handoff_anchors must be >= 0");
+        if (t->handoff_anchors[k] < 0 || t->batch_handoff_anchors[k] < 0)
+            return fail(c, DMT_E_INVALID, "handoff_anchors and batch_handoff_anchors must be >= 0");
         if (t->grid_iterations[k] < 1 || t->grid_iterations[k] > 4096)
             return fail(c, DMT_E_INVALID, "grid_iterations must be in 1..4096");
     }

@@ -79,7 +79,7 @@ class dmt_stats(C.Structure):
 
 class dmt_tuning(C.Structure):
     _fields_ = [("loop_threads", C.c_int32 * 2), ("handoff_anchors", C.c_int32 * 2),
-                ("grid_iterations", C.c_int32 * 2)]
+                ("grid_iterations", C.c_int32 * 2), ("batch_handoff_anchors", C.c_int32 * 2)]
 
     def as_dict(self) -> Dict[str, list]:
         return {k: list(getattr(self, k)) for k, _ in self._fields_}
@@ -443,11 +443,13 @@ def dmt_correct_noalloc(ctx: Context, f: torch.Tensor, g_hat: torch.Tensor, xi: 
 
 def dmt_set_tuning(ctx: Context, tuning: Optional[Dict[str, list]] = None) -> None:
     """Sets the loop's launch shapes ({"loop_threads": [2D, 3D], "handoff_anchors": [2D, 3D],
-    "grid_iterations": [single, batch]}); None restores the defaults."""
+    "grid_iterations": [single, batch], "batch_handoff_anchors": [2D, 3D]}); keys left out keep
+    the context's current values.  None restores the defaults."""
     if tuning is None:
         ctx.check(ctx.L.dmt_set_tuning(ctx.h, None))
         return
     t = dmt_tuning()
+    ctx.check(ctx.L.dmt_get_tuning(ctx.h, C.byref(t)))
     for k, v in tuning.items():
         arr = getattr(t, k)
         arr[0], arr[1] = int(v[0]), int(v[1])

@@ -301,7 +301,8 @@ def test_correct_batch_concurrent_handoff(ctx, dmt, threads):
     choice of loop workgroup sizes."""
     ws = _batch_jobs()
     fields = [(_t(w.f), _t(w.g_hat), w.xi) for w in ws]
-    dmt.dmt_set_tuning(ctx, {"loop_threads": list(threads), "handoff_anchors": [16, 16], "grid_iterations": [4, 2]})
+    dmt.dmt_set_tuning(ctx, {"loop_threads": list(threads), "handoff_anchors": [8192, 8192], "grid_iterations": [4, 2],
+                             "batch_handoff_anchors": [16, 16]})
     try:
         res = dmt.dmt_correct_batch(ctx, fields, tier=4, q_max=6)
     finally:
@@ -337,12 +338,28 @@ def test_tuning_keeps_results(ctx, dmt, threads, limit):
 def test_tuning_rejects_bad_values(ctx, dmt):
     before = dmt.dmt_get_tuning(ctx)
     for bad in ({"loop_threads": [256, 512]}, {"loop_threads": [1024, 1024]}, {"handoff_anchors": [-1, 0]},
-                {"grid_iterations": [0, 4]}, {"grid_iterations": [4, 5000]}):
+                {"grid_iterations": [0, 4]}, {"grid_iterations": [4, 5000]}, {"batch_handoff_anchors": [0, -1]}):
         t = {k: list(v) for k, v in before.items()}
         t.update(bad)
         with pytest.raises(dmt.DmtError):
             dmt.dmt_set_tuning(ctx, t)
         assert dmt.dmt_get_tuning(ctx) == before
+
+
+def test_tuning_keys_left_out_keep_their_values(ctx, dmt):
+    """A partial setting changes only the keys it names; None restores the defaults."""
+    dmt.dmt_set_tuning(ctx, None)
+    default = dmt.dmt_get_tuning(ctx)
+    assert default["handoff_anchors"] == [8192, 1024] and default["batch_handoff_anchors"] == [8192, 8192]
+    try:
+        dmt.dmt_set_tuning(ctx, {"batch_handoff_anchors": [16, 32]})
+        t = dmt.dmt_get_tuning(ctx)
+        assert t["batch_handoff_anchors"] == [16, 32]
+        assert {k: v for k, v in t.items() if k != "batch_handoff_anchors"} == \
+            {k: v for k, v in default.items() if k != "batch_handoff_anchors"}
+    finally:
+        dmt.dmt_set_tuning(ctx, None)
+    assert dmt.dmt_get_tuning(ctx) == default
 
 
 def test_autotuner_picks_a_setting(ctx, dmt):
