@@ -726,7 +726,8 @@ __device__ __forceinline__ void phase_grad(const FrontierView& B, const Dims& dm
     if constexpr (!WG) {
         // Dense iteration (full-grid form): when the last violation pass made no lists, or its
         // lists cover more than 1/DENSE_DIV of the grid, every vertex's gradient is recomputed and
-        // copied across, and the violation pass classifies every anchor, as at iteration 0.  The
+        // copied across, and a classification pass (k_fr_classify_dense) classifies every anchor
+        // and lists the violating ones for the violation pass, as at iteration 0.  The
         // frozen anchors are all revived (their masks are recomputed) and the first differing
         // cell of every branch is found afresh.  It is the frontier iteration with every vertex
         // dirty and every anchor affected, which gives the same result.
@@ -876,6 +877,9 @@ __device__ __forceinline__ void touched_cells(const FrontierView& B, const Dims&
     }
 }
 
+template <int D>
+__device__ __forceinline__ void cand_rebuild(const FrontierView& B, int gtid, int gsize);
+
 // Pass B (phase_bscan): for each marked branch, if its old first cell still differs the new
 // first is the smaller of it and newmin; otherwise the first differing cell after the old first
 // (searched only up to newmin), else newmin.  One wave per branch, 64 cells per step.  The
@@ -959,14 +963,14 @@ __device__ __forceinline__ void phase_vr(const FrontierView& B, const Dims& dm, 
     int cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     int rc[2] = {0, 0};
     // One index space: the affected anchors get new masks; the anchors listed by the previous
-    // iteration and not affected since keep theirs.  Iteration 0 takes the violating anchors the
-    // classification pass listed (masks computed there); a dense iteration after it (full-grid
-    // form, see phase_grad) takes every anchor as affected.
+    // iteration and not affected since keep theirs.  Iteration 0, and a dense iteration after it
+    // (full-grid form, see phase_grad: every anchor affected), take the violating anchors that
+    // the classification pass listed in vl[it & 1], with their masks computed there.
     const bool first = it == 0;
     bool all = false;
     if constexpr (!WG) all = !first && ld_relaxed(&B.ctl->dense) != 0;
     const bool dense = first || all;
-    const int na = first ? ld_relaxed(&B.ctl->n_v0) : all ? dm.n : ld_relaxed(&S.n_da);
+    const int na = dense ? ld_relaxed(&B.ctl->n_v0) : ld_relaxed(&S.n_da);
     const int nl = dense ? 0 : ld_relaxed(&S.n_vl);
     const int ntot = na + nl;
     // a dense iteration after the first, whose previous iteration edited more than 1/NOMARK_DIV
@@ -999,11 +1003,11 @@ __device__ __forceinline__ void phase_vr(const FrontierView& B, const Dims& dm, 
         uint64_t fpk = 0;   // the anchor's f codes, when loaded here (2D)
         int a = 0;
         bool listed = false;
-        if (i0 < na && first) {
-            a = B.vl[0][i0];
+        if (i0 < na && dense) {
+            a = vlist[i0];
             m = B.vmask[a];
         } else if (i0 < na) {
-            a = all ? i0 : alist[i0];
+            a = alist[i0];
             int x, y, z;
             coords(dm, a, x, y, z);
             m = vmask_anchor<D>(dm, a, x, y, z, B.fpl, B.gpl, B.tier, &fpk);
@@ -1034,12 +1038,12 @@ __device__ __forceinline__ void phase_vr(const FrontierView& B, const Dims& dm, 
     }
     // first differing cell of the f-branches, kept up to date for the separatrix step: every
     // branch at iteration 0 (first[] starts at INF32), afterwards the branches listed by the
-    // gradient pass
+    // gradient pass (a later dense iteration's classification pass scans every branch)
     if (B.tier >= 3) {
-        if (dense) {
+        if (first) {
             dense_first_scan<D>(B, dm, false, gtid, gsize);
             dense_first_scan<D>(B, dm, true, gtid, gsize);
-        } else {
+        } else if (!all) {
             touched_cells<D, WG>(B, dm, it, gtid, gsize);
         }
     }
@@ -1636,39 +1640,68 @@ __global__ void __launch_bounds__(256) k_fr_grad(FrontierBufs hb, Dims dm) {
     phase_grad<D>(B, dm, ld_relaxed(&B.ctl->it), blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
 }
 
-// Iteration 0's critical-cell classification as a streaming pass (a4): every anchor's violation
-// mask from its f and g codes in every plane (each plane a byte array, read once, coalesced) and
-// the list of violating anchors in vl[0], compacted by wave ballot and a block-wide prefix sum with
-// one atomic per block; the violation pass of iteration 0 then requests targets for the listed
-// anchors only.
-constexpr int CLASSIFY_APB = 1024;   // anchors per block of k_fr_classify0
+// The critical-cell classification as a streaming pass (a4): every anchor's violation mask from
+// its f and g codes in every plane (each plane a byte array, read once, coalesced) and the list of
+// violating anchors, compacted by wave ballot and a block-wide prefix sum with one atomic per
+// chunk (count in ctl->n_v0, 0 before).  A block takes chunks of CLASSIFY_APB consecutive anchors
+// (chunk c0, c0 + cstep, ...); thread t takes those at t + k * 256 of a chunk (coalesced).  The
+// violation pass then requests targets for the listed anchors only.
+constexpr int CLASSIFY_APB = 1024;   // anchors per chunk
+template <int D>
+__device__ __forceinline__ void classify_chunks(const FrontierView& B, const Dims& dm, int* list, int c0, int cstep) {
+    const int nchunks = (int)((dm.n + CLASSIFY_APB - 1) / CLASSIFY_APB);
+    __shared__ int base_sh;
+    for (int ch = c0; ch < nchunks; ch += cstep) {
+        const int a0 = ch * CLASSIFY_APB;
+        uint32_t m[CLASSIFY_APB / 256];
+        int c = 0;
+#pragma unroll
+        for (int k = 0; k < CLASSIFY_APB / 256; k++) {
+            const int a = a0 + k * 256 + (int)threadIdx.x;
+            m[k] = 0;
+            if (a < dm.n) {
+                int x, y, z;
+                coords(dm, a, x, y, z);
+                m[k] = vmask_anchor<D>(dm, a, x, y, z, B.fpl, B.gpl, B.tier);
+                B.vmask[a] = m[k];
+            }
+            c += m[k] != 0;
+        }
+        int total;
+        int off = block_exclusive_scan(c, total);
+        if (threadIdx.x == 0 && total) base_sh = atomicAdd(&B.ctl->n_v0, total);
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < CLASSIFY_APB / 256; k++)
+            if (m[k] != 0) list[base_sh + off++] = a0 + k * 256 + (int)threadIdx.x;
+        __syncthreads();   // base_sh is written again for the next chunk
+    }
+}
+
+// Iteration 0's classification: one chunk per block, the list in vl[0].
 template <int D>
 __global__ void __launch_bounds__(256) k_fr_classify0(FrontierBufs hb, Dims dm) {
     const FrontierView& B = view(hb);
-    int* list = B.vl[0];
-    // a block takes CLASSIFY_APB consecutive anchors, thread t those at t + k * 256 (coalesced)
-    uint32_t m[CLASSIFY_APB / 256];
-    int c = 0;
-#pragma unroll
-    for (int k = 0; k < CLASSIFY_APB / 256; k++) {
-        const int a = blockIdx.x * CLASSIFY_APB + k * 256 + threadIdx.x;
-        m[k] = 0;
-        if (a < dm.n) {
-            int x, y, z;
-            coords(dm, a, x, y, z);
-            m[k] = vmask_anchor<D>(dm, a, x, y, z, B.fpl, B.gpl, B.tier);
-            B.vmask[a] = m[k];
-        }
-        c += m[k] != 0;
+    classify_chunks<D>(B, dm, B.vl[0], blockIdx.x, gridDim.x);
+}
+
+// The classification of a dense iteration after the first (full-grid form, see phase_grad), as
+// at iteration 0: the list goes to vl[it & 1], which a dense iteration's violation pass does not
+// otherwise read (it has no anchors listed by the previous iteration).  The violation pass keeps
+// its heavy per-anchor code, with few waves per SIMD, for the violating anchors alone.  Then the
+// first differing cell of every branch (first[] reset by the gradient pass).  Returns at once
+// when the iteration is not dense; launched on a capped grid, so that costs little.
+template <int D>
+__global__ void __launch_bounds__(256) k_fr_classify_dense(FrontierBufs hb, Dims dm) {
+    const FrontierView& B = view(hb);
+    if (!running(B.ctl) || ld_relaxed(&B.ctl->dense) == 0) return;
+    const int it = ld_relaxed(&B.ctl->it);
+    classify_chunks<D>(B, dm, B.vl[it & 1], blockIdx.x, gridDim.x);
+    if (B.tier >= 3) {
+        const int gtid = blockIdx.x * blockDim.x + threadIdx.x, gsize = gridDim.x * blockDim.x;
+        dense_first_scan<D>(B, dm, false, gtid, gsize);
+        dense_first_scan<D>(B, dm, true, gtid, gsize);
     }
-    __shared__ int base_sh;
-    int total;
-    int off = block_exclusive_scan(c, total);
-    if (threadIdx.x == 0 && total) base_sh = atomicAdd(&B.ctl->n_v0, total);
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < CLASSIFY_APB / 256; k++)
-        if (m[k] != 0) list[base_sh + off++] = blockIdx.x * CLASSIFY_APB + k * 256 + threadIdx.x;
 }
 
 template <int D>

@@ -71,7 +71,13 @@ struct DevBuf {
 
 constexpr int TPB = 256;
 constexpr int HAND_STREAMS = 4;  // streams for the grid iterations of paused batch jobs
+constexpr int GRID_RUN_MAX = 16;  // longest doubled hand-off run (grid_iterations if that is more)
 inline unsigned nblocks(int64_t n) { return (unsigned)((n + TPB - 1) / TPB); }
+// blocks of a classification launch: one per chunk of CLASSIFY_APB anchors, at most cap
+inline unsigned classify_blocks(int64_t n, unsigned cap = ~0u) {
+    const unsigned b = (unsigned)((n + CLASSIFY_APB - 1) / CLASSIFY_APB);
+    return b < cap ? b : cap;
+}
 
 // Critical cells and separatrix branches of one gradient (device arrays, int32 ids).
 struct MscBufs {
@@ -649,7 +655,7 @@ dmt_status job_iteration0(dmt_context* c, Job& J, hipStream_t st) {
     }
     {
         ProfScope ps(c, DMT_PROF_CLASSIFY, st, n);
-        k_fr_classify0<D><<<(unsigned)((n + CLASSIFY_APB - 1) / CLASSIFY_APB), TPB, 0, st>>>(J.B, J.dm);
+        k_fr_classify0<D><<<classify_blocks(n), TPB, 0, st>>>(J.B, J.dm);
         CHECK_LAUNCH(c);
     }
     // the requests (and edits) of iteration 0's violations
@@ -691,6 +697,7 @@ template <int D>
 dmt_status grid_iterations(dmt_context* c, const FrontierBufs& B, const Dims& dm, int K, bool from_sstep,
                            hipStream_t st) {
     const unsigned gfull = nblocks(dm.n) < 2048u ? nblocks(dm.n) : 2048u;
+    const unsigned gcls = classify_blocks(dm.n, 2048u);
     if (from_sstep) {
         // paused before the troublemaker pass of iteration ctl->it: finish that iteration first
         k_fr_sapply<D><<<gfull, TPB, 0, st>>>(B, dm);
@@ -699,6 +706,7 @@ dmt_status grid_iterations(dmt_context* c, const FrontierBufs& B, const Dims& dm
     }
     for (int k = 0; k <= K; k++) {
         k_fr_grad<D><<<gfull, TPB, 0, st>>>(B, dm);
+        k_fr_classify_dense<D><<<gcls, TPB, 0, st>>>(B, dm);
         k_fr_vr<D><<<gfull, TPB, 0, st>>>(B, dm);
         k_fr_bscan<D><<<gfull, TPB, 0, st>>>(B, dm);
         if (k == K) break;
@@ -763,6 +771,13 @@ dmt_status run_wg(dmt_context* c, std::vector<Job*>& jobs, bool with_log, hipStr
     std::vector<int> pos(nj);
     for (int k = 0; k < nj; k++) pos[order[k]] = k;
     const int grid_batch = c->tune.grid_iterations[nj == 1 ? 0 : 1];
+    // a job that pauses again at once after a hand-off (its next iteration is large as well) gets
+    // twice as many grid iterations at its next hand-off, up to GRID_RUN_MAX; one that ran
+    // iterations in the workgroup in between starts again from grid_batch.  This saves the loop
+    // relaunches and host round trips of long runs of large iterations.
+    const int krun_max = std::max(grid_batch, GRID_RUN_MAX);
+    std::vector<int> krun(nj, grid_batch);
+    std::vector<int64_t> resume_it(nj, -2);
     int64_t progress = -1;
     for (int launch = 0; max_launches < 0 || launch < max_launches; launch++) {
         HIPCHK(c, hipMemsetAsync(c->queue.p, 0, sizeof(int) * 2, st));
@@ -844,9 +859,12 @@ dmt_status run_wg(dmt_context* c, std::vector<Job*>& jobs, bool with_log, hipStr
                 // a large iteration: reset the pause and make room in the log (on st, before the fork)
                 const Job* J = jobs[j];
                 FrontierBufs& hj = hb[pos[j]];
-                const int64_t it0 = c->hctl[jobs[j]->slot].it;
-                if (with_log && it0 + grid_batch + 2 > hj.log_cap) {
-                    TRY(grow_log(c, (size_t)(it0 + grid_batch) * 2 + 4096, it0, st));
+                const Ctl& h = c->hctl[J->slot];
+                const int64_t it0 = h.it;
+                krun[j] = it0 <= resume_it[j] + 1 ? std::min(krun[j] * 2, krun_max) : grid_batch;
+                resume_it[j] = it0 + krun[j] + (h.paused == 2);
+                if (with_log && it0 + krun[j] + 2 > hj.log_cap) {
+                    TRY(grow_log(c, (size_t)(it0 + krun[j]) * 2 + 4096, it0, st));
                     hj.log = P<long long>(c->dlog);
                     hj.log_cap = (int)(c->dlog.cap / (sizeof(long long) * DMT_LOG_WORDS));
                     HIPCHK(c, hipMemcpyAsync(P<FrontierBufs>(c->jobs_dev) + pos[j], &hj, sizeof(FrontierBufs),
@@ -864,8 +882,8 @@ dmt_status run_wg(dmt_context* c, std::vector<Job*>& jobs, bool with_log, hipStr
                 const Job* J = jobs[j];
                 const bool from_sstep = c->hctl[J->slot].paused == 2;
                 hipStream_t hs = ns > 1 ? c->hand[i % ns] : st;
-                TRY(J->D == 2 ? grid_iterations<2>(c, hb[pos[j]], J->dm, grid_batch, from_sstep, hs)
-                              : grid_iterations<3>(c, hb[pos[j]], J->dm, grid_batch, from_sstep, hs));
+                TRY(J->D == 2 ? grid_iterations<2>(c, hb[pos[j]], J->dm, krun[j], from_sstep, hs)
+                              : grid_iterations<3>(c, hb[pos[j]], J->dm, krun[j], from_sstep, hs));
             }
             if (ns > 1) {
                 for (int k = 0; k < ns; k++) {
@@ -891,6 +909,7 @@ template <int D>
 dmt_status run_phases(dmt_context* c, Job& J, hipStream_t st) {
     const int n = J.dm.n;
     const unsigned gfull = nblocks(n) < 2048u ? nblocks(n) : 2048u;
+    const unsigned gcls = classify_blocks(n, 2048u);
     int batch = 4;
     Ctl h{};
     // iteration 0 (dense passes), the first troublemaker candidates, and its decision
@@ -899,7 +918,7 @@ dmt_status run_phases(dmt_context* c, Job& J, hipStream_t st) {
     {
         ProfScope ps(c, DMT_PROF_LOOP, st, 0);
         k_fr_grad<D><<<gfull, TPB, 0, st>>>(J.B, J.dm);
-        k_fr_classify0<D><<<(unsigned)((n + CLASSIFY_APB - 1) / CLASSIFY_APB), TPB, 0, st>>>(J.B, J.dm);
+        k_fr_classify0<D><<<classify_blocks(n), TPB, 0, st>>>(J.B, J.dm);
         k_fr_vr<D><<<gfull, TPB, 0, st>>>(J.B, J.dm);
         const int64_t nbr = (int64_t)J.B.n_desc + J.B.n_asc;
         if (nbr) k_fr_cand_init<D><<<nblocks((nbr + CAND_PER_THREAD - 1) / CAND_PER_THREAD), TPB, 0, st>>>(J.B, J.B.ctl);
@@ -915,6 +934,7 @@ dmt_status run_phases(dmt_context* c, Job& J, hipStream_t st) {
         for (int b = 0; b < batch; b++) {
             ProfScope ps(c, DMT_PROF_LOOP, st, 0);
             k_fr_grad<D><<<gfull, TPB, 0, st>>>(J.B, J.dm);
+            k_fr_classify_dense<D><<<gcls, TPB, 0, st>>>(J.B, J.dm);
             k_fr_vr<D><<<gfull, TPB, 0, st>>>(J.B, J.dm);
             k_fr_bscan<D><<<gfull, TPB, 0, st>>>(J.B, J.dm);
             if (J.o.tier >= 3) k_fr_sapply<D><<<gfull, TPB, 0, st>>>(J.B, J.dm);
