@@ -185,21 +185,26 @@ def test_correct_hybrid_handoff(ctx, dmt, limit, case):
     assert (log[:, 14] + log[:, 15] > limit).any(), "the hand-off was not exercised"
 
 
-@pytest.mark.parametrize("case", ["extreme64", "tiny3d", "atoms3d40"])
-def test_correct_dense_iterations(ctx, dmt, case):
-    """With every iteration handed to the full grid, the iterations whose lists cover more than a
-    quarter of the grid run densely (every vertex dirty, every anchor affected), and a dense
-    iteration after one that edited more than 1/32 of the vertices makes no lists (its successor
-    is dense too): results and log stay those of the oracle, and the log shows both kinds."""
-    if case == "extreme64":
+@pytest.mark.parametrize("flags", [0, 2], ids=["handoff", "phases"])
+@pytest.mark.parametrize("case", ["extreme64", "extreme64-tier2", "tiny3d", "atoms3d40"])
+def test_correct_dense_iterations(ctx, dmt, case, flags):
+    """With every iteration on the full grid (hand-off limit 1, or the per-phase form), the
+    iterations whose lists cover more than a quarter of the grid run densely (every vertex dirty,
+    every anchor classified by the streaming pass, which also scans every branch from tier 3),
+    and a dense iteration after one that edited more than 1/32 of the vertices makes no lists (its
+    successor is dense too): results and log stay those of the oracle, and the log shows both
+    kinds."""
+    tier = None
+    if case.startswith("extreme64"):
         w = synth.extreme_noise2d(64, 1)
+        tier = 2 if case.endswith("tier2") else None
     elif case == "tiny3d":
         w = synth.tiny_cases(13, (12, 10, 9), rel=0.05, kind="smooth", ghat="noise")
     else:
         w = synth.config_atoms3d(seed=3, side=40, n_atoms=24)
     dmt.dmt_set_tuning(ctx, {"loop_threads": [1024, 512], "handoff_anchors": [1, 1], "grid_iterations": [4, 64]})
     try:
-        r, o = _compare_correction(ctx, dmt, w)
+        r, o = _compare_correction(ctx, dmt, w, tier=tier, flags=flags)
     finally:
         dmt.dmt_set_tuning(ctx, None)
     n = w.f.size
