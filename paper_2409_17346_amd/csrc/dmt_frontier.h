@@ -66,7 +66,8 @@ struct Ctl {
     unsigned long long dead_distinct;
     int n_ftgt;
     int n_dead;             // frozen anchors (in LDS while the resident loop runs)
-    int n_v0;               // violating anchors of iteration 0 (k_fr_classify0), listed in vl[0]
+    int n_v0;               // violating anchors listed by a classification pass: iteration 0's in
+                            // vl[0], a later dense iteration's in vl[it & 1]
     // full-grid form: the current iteration is dense (every vertex and anchor, see phase_grad);
     // nomark: the last violation pass made no dirty/affected lists, so the next iteration is dense
     int dense, nomark;
