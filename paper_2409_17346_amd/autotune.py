@@ -24,7 +24,7 @@ CANDIDATES: Dict[Tuple[str, int], Sequence[int]] = {
     ("handoff_anchors", 0): (2048, 8192, 32768),
     ("handoff_anchors", 1): (1024, 8192, 32768),
     ("grid_iterations", 0): (2, 4, 16),
-    ("grid_iterations", 1): (16, 64, 256),
+    ("grid_iterations", 1): (4, 16, 64, 256),
     ("batch_handoff_anchors", 0): (2048, 8192, 32768),
     ("batch_handoff_anchors", 1): (2048, 8192, 32768),
 }
