@@ -462,6 +462,10 @@ struct Job {
     FrontierBufs B{};
     dmt_stats stats{};
     dmt_status status = DMT_OK;
+    // hand-off run length (grid iterations) and the iteration its last run ended at; kept with the
+    // job, so that a served job's runs keep growing across the server's rounds
+    int krun = 0;
+    int64_t resume_it = -2;
 };
 
 // a0 (floors, validation flag into *flag) and a1 (gradient of f): launches only.
@@ -776,8 +780,6 @@ dmt_status run_wg(dmt_context* c, std::vector<Job*>& jobs, bool with_log, hipStr
     // iterations in the workgroup in between starts again from grid_batch.  This saves the loop
     // relaunches and host round trips of long runs of large iterations.
     const int krun_max = std::max(grid_batch, GRID_RUN_MAX);
-    std::vector<int> krun(nj, grid_batch);
-    std::vector<int64_t> resume_it(nj, -2);
     int64_t progress = -1;
     for (int launch = 0; max_launches < 0 || launch < max_launches; launch++) {
         HIPCHK(c, hipMemsetAsync(c->queue.p, 0, sizeof(int) * 2, st));
@@ -857,14 +859,14 @@ dmt_status run_wg(dmt_context* c, std::vector<Job*>& jobs, bool with_log, hipStr
             }
             for (int j : paused) {
                 // a large iteration: reset the pause and make room in the log (on st, before the fork)
-                const Job* J = jobs[j];
+                Job* J = jobs[j];
                 FrontierBufs& hj = hb[pos[j]];
                 const Ctl& h = c->hctl[J->slot];
                 const int64_t it0 = h.it;
-                krun[j] = it0 <= resume_it[j] + 1 ? std::min(krun[j] * 2, krun_max) : grid_batch;
-                resume_it[j] = it0 + krun[j] + (h.paused == 2);
-                if (with_log && it0 + krun[j] + 2 > hj.log_cap) {
-                    TRY(grow_log(c, (size_t)(it0 + krun[j]) * 2 + 4096, it0, st));
+                J->krun = it0 <= J->resume_it + 1 ? std::min(J->krun * 2, krun_max) : grid_batch;
+                J->resume_it = it0 + J->krun + (h.paused == 2);
+                if (with_log && it0 + J->krun + 2 > hj.log_cap) {
+                    TRY(grow_log(c, (size_t)(it0 + J->krun) * 2 + 4096, it0, st));
                     hj.log = P<long long>(c->dlog);
                     hj.log_cap = (int)(c->dlog.cap / (sizeof(long long) * DMT_LOG_WORDS));
                     HIPCHK(c, hipMemcpyAsync(P<FrontierBufs>(c->jobs_dev) + pos[j], &hj, sizeof(FrontierBufs),
@@ -882,8 +884,8 @@ dmt_status run_wg(dmt_context* c, std::vector<Job*>& jobs, bool with_log, hipStr
                 const Job* J = jobs[j];
                 const bool from_sstep = c->hctl[J->slot].paused == 2;
                 hipStream_t hs = ns > 1 ? c->hand[i % ns] : st;
-                TRY(J->D == 2 ? grid_iterations<2>(c, hb[pos[j]], J->dm, krun[j], from_sstep, hs)
-                              : grid_iterations<3>(c, hb[pos[j]], J->dm, krun[j], from_sstep, hs));
+                TRY(J->D == 2 ? grid_iterations<2>(c, hb[pos[j]], J->dm, J->krun, from_sstep, hs)
+                              : grid_iterations<3>(c, hb[pos[j]], J->dm, J->krun, from_sstep, hs));
             }
             if (ns > 1) {
                 for (int k = 0; k < ns; k++) {
